@@ -164,6 +164,15 @@ def rel_err(a: float, b: float, t: float = 1.0) -> float:
     return abs(a - b) / max(abs(b), 1e-3 * t)
 
 
+def _logged_near(g) -> bool:
+    """Near-threshold flag of a logged update: a dict with key 'near', or a
+    record with bit 0 of 'flags'."""
+    if isinstance(g, dict):
+        return bool(g.get("near", False))
+    names = getattr(getattr(g, "dtype", None), "names", None) or ()
+    return bool(int(g["flags"]) & 1) if "flags" in names else False
+
+
 def replay_sweep(S, prm: Params, T: float, sweep: int, gpu_log, eig=eigvals_lapack,
                  rel_tau=1e-9, check=None):
     """Re-run one sweep update by update next to a logged trajectory.
@@ -193,7 +202,7 @@ def replay_sweep(S, prm: Params, T: float, sweep: int, gpu_log, eig=eigvals_lapa
             stats["rels"].append(e)
             stats["max_rel"] = max(stats["max_rel"], e)
             stats["max_abs"] = max(stats["max_abs"], abs(float(g["dF"]) - r["dF"]))
-            flag = r["near"] or bool(g.get("near", False))
+            flag = r["near"] or _logged_near(g)
             stats["flagged"] += int(flag)
             if bool(g["accept"]) != r["accept"]:
                 if flag:

@@ -1,0 +1,250 @@
+"""Python binding of libtca.so, the MI355X (gfx950) HIP implementation of the
+parallelized traveling cluster approximation (arXiv:1502.07028).
+
+Argument marshalling only: every step of the Monte Carlo hot path runs in the
+library's HIP kernels.  The functions carry the C names of ``include/tca.h``.
+Importing this module raises if the HIP library has not been built
+(``python -m paper_1502_07028_amd.build``); there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtca.so")
+
+TCA_ABI_VERSION = 1
+TCA_OK, TCA_E_INVAL, TCA_E_NOMEM, TCA_E_DEVICE, TCA_E_UNSUPPORTED = 0, -1, -2, -3, -4
+TCA_FP64, TCA_MIXED = 0, 1
+TCA_INIT_RANDOM, TCA_INIT_FERRO, TCA_INIT_NEEL, TCA_INIT_USER = 0, 1, 2, 3
+TCA_FLAG_PROFILE = 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python -m paper_1502_07028_amd.build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class tca_params(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("L", ctypes.c_int32), ("Lc", ctypes.c_int32),
+                ("n_classes", ctypes.c_int32), ("Lc_classes", ctypes.c_int32 * 4),
+                ("t", ctypes.c_double), ("JH", ctypes.c_double), ("JAF", ctypes.c_double),
+                ("mu", ctypes.c_double), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("init", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class tca_update_record(ctypes.Structure):
+    _fields_ = [("site", ctypes.c_int32), ("Lc", ctypes.c_int16), ("accept", ctypes.c_uint8),
+                ("flags", ctypes.c_uint8), ("dF", ctypes.c_double), ("dE", ctypes.c_double),
+                ("u", ctypes.c_double)]
+
+
+class tca_sweep_stats(ctypes.Structure):
+    _fields_ = [("updates", ctypes.c_int64), ("accepted", ctypes.c_int64),
+                ("near_threshold", ctypes.c_int64), ("elapsed_ms", ctypes.c_double),
+                ("cluster_ms", ctypes.c_double), ("decide_ms", ctypes.c_double),
+                ("cluster_launches", ctypes.c_int64), ("decide_launches", ctypes.c_int64)]
+
+
+RECORD_DTYPE = np.dtype([("site", "<i4"), ("Lc", "<i2"), ("accept", "u1"), ("flags", "u1"),
+                         ("dF", "<f8"), ("dE", "<f8"), ("u", "<f8")])
+assert RECORD_DTYPE.itemsize == ctypes.sizeof(tca_update_record)
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+_SIGS = {
+    "tca_init_lattice": [ctypes.POINTER(tca_params), _D, _P, ctypes.POINTER(_P)],
+    "tca_sweep": [_P, _D, ctypes.c_int32, _P, ctypes.POINTER(tca_sweep_stats)],
+    "tca_cluster_eigvals": [_P, _I, _I, _D, ctypes.c_int32, _D, ctypes.c_int32],
+    "tca_observables": [_P, _D, _D, _D],
+    "tca_set_state": [_P, _D, ctypes.c_uint64],
+    "tca_get_sweep_counter": [_P, ctypes.POINTER(ctypes.c_uint64)],
+    "tca_heevals_batched": [_D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                            ctypes.c_double, _D, _D],
+    "tca_heevals_batched_dev": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_double, ctypes.c_double, _P, _P, _P],
+    "tca_destroy": [_P],
+    "tca_abi_sizes": [_I],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.tca_strerror.argtypes = [ctypes.c_int]
+_lib.tca_strerror.restype = ctypes.c_char_p
+_lib.tca_last_error.argtypes = []
+_lib.tca_last_error.restype = ctypes.c_char_p
+
+
+class TCAError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.tca_last_error().decode() or _lib.tca_strerror(status).decode()
+        super().__init__(f"{where}: {_lib.tca_strerror(status).decode()} ({status}): {msg}")
+
+
+def _check(status, where):
+    if status != TCA_OK:
+        raise TCAError(status, where)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def tca_abi_sizes():
+    out = np.zeros(3, dtype=np.int32)
+    _check(_lib.tca_abi_sizes(out.ctypes.data_as(_I)), "tca_abi_sizes")
+    return tuple(int(x) for x in out)
+
+
+def make_params(L, Lc=8, t=1.0, JH=8.0, JAF=0.0, mu=0.0, seed=1, precision=TCA_FP64,
+                init=TCA_INIT_RANDOM, Lc_classes=(), flags=0):
+    p = tca_params()
+    p.abi_version = TCA_ABI_VERSION
+    p.L, p.Lc = int(L), int(Lc)
+    p.n_classes = len(Lc_classes)
+    for k, v in enumerate(Lc_classes):
+        p.Lc_classes[k] = int(v)
+    p.t, p.JH, p.JAF, p.mu = float(t), float(JH), float(JAF), float(mu)
+    p.seed = int(seed)
+    p.precision, p.init = int(precision), int(init)
+    p.flags = int(flags)
+    return p
+
+
+def tca_init_lattice(params, spins=None, stream=None):
+    """Create a context; returns an opaque handle (int).  ``stream`` is a raw
+    hipStream_t (e.g. ``torch.cuda.current_stream().cuda_stream``) or None."""
+    sp = None if spins is None else _f64(spins, (-1, 3))
+    h = _P()
+    _check(_lib.tca_init_lattice(ctypes.byref(params), _dptr(sp), stream, ctypes.byref(h)),
+           "tca_init_lattice")
+    return h.value
+
+
+def tca_destroy(ctx):
+    _check(_lib.tca_destroy(ctx), "tca_destroy")
+
+
+def tca_sweep(ctx, T, nsweeps=None, log=False, N=None):
+    """Run sweeps at temperatures T (array, one per sweep).  Returns
+    (records or None, stats dict)."""
+    T = _f64(np.atleast_1d(T))
+    ns = len(T) if nsweeps is None else int(nsweeps)
+    recs = None
+    if log:
+        if N is None:
+            raise ValueError("N (lattice sites) is needed to size the log")
+        recs = np.zeros(ns * N, dtype=RECORD_DTYPE)
+    st = tca_sweep_stats()
+    _check(_lib.tca_sweep(ctx, _dptr(T), ns, recs.ctypes.data if recs is not None else None,
+                          ctypes.byref(st)), "tca_sweep")
+    return recs, dict(updates=st.updates, accepted=st.accepted,
+                      near_threshold=st.near_threshold, elapsed_ms=st.elapsed_ms,
+                      cluster_ms=st.cluster_ms, decide_ms=st.decide_ms,
+                      cluster_launches=st.cluster_launches, decide_launches=st.decide_launches)
+
+
+def tca_cluster_eigvals(ctx, sites, Lc=None, proposed=None, ld=None):
+    sites = np.ascontiguousarray(sites, dtype=np.int32)
+    n = len(sites)
+    lcs = None if Lc is None else np.ascontiguousarray(np.broadcast_to(Lc, (n,)), dtype=np.int32)
+    if ld is None:
+        ld = 2 * int(np.max(lcs)) ** 2 if lcs is not None else 200
+    prop = None if proposed is None else _f64(proposed, (n, 3))
+    out = np.full((n, ld), np.nan)
+    _check(_lib.tca_cluster_eigvals(ctx, sites.ctypes.data_as(_I),
+                                    lcs.ctypes.data_as(_I) if lcs is not None else None,
+                                    _dptr(prop), n, _dptr(out), ld), "tca_cluster_eigvals")
+    return out
+
+
+def tca_observables(ctx, L):
+    N = L * L
+    spins = np.zeros((N, 3))
+    sq = np.zeros((L, L))
+    m = np.zeros(3)
+    _check(_lib.tca_observables(ctx, _dptr(spins), _dptr(sq), _dptr(m)), "tca_observables")
+    return spins, sq, m
+
+
+def tca_set_state(ctx, spins, sweep_counter):
+    sp = _f64(spins, (-1, 3))
+    _check(_lib.tca_set_state(ctx, _dptr(sp), int(sweep_counter)), "tca_set_state")
+
+
+def tca_get_sweep_counter(ctx):
+    v = ctypes.c_uint64()
+    _check(_lib.tca_get_sweep_counter(ctx, ctypes.byref(v)), "tca_get_sweep_counter")
+    return v.value
+
+
+def tca_heevals_batched(A, precision=TCA_FP64, T=None, mu=0.0):
+    """A: (batch, n, n) complex Hermitian.  Returns (eigenvalues (batch, n),
+    free energies (batch,) or None)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    batch, n, _ = A.shape
+    w = np.zeros((batch, n))
+    F = np.zeros(batch) if T is not None else None
+    Ad = A.view(np.float64)
+    _check(_lib.tca_heevals_batched(_dptr(Ad), n, batch, precision,
+                                    float(T) if T is not None else 1.0, float(mu), _dptr(w),
+                                    _dptr(F)), "tca_heevals_batched")
+    return w, F
+
+
+def tca_heevals_batched_dev(A_ptr, n, batch, precision, T, mu, w_ptr, F_ptr, stream):
+    """Device-pointer variant (raw addresses, e.g. tensor.data_ptr())."""
+    _check(_lib.tca_heevals_batched_dev(A_ptr, n, batch, precision, float(T), float(mu),
+                                        w_ptr, F_ptr, stream), "tca_heevals_batched_dev")
+
+
+class Lattice:
+    """Owning wrapper of one tca_ctx."""
+
+    def __init__(self, L, Lc=8, stream=None, spins=None, **kw):
+        if spins is not None:
+            kw["init"] = TCA_INIT_USER
+        self.L, self.N = int(L), int(L) * int(L)
+        self.params = make_params(L, Lc, **kw)
+        self.ctx = tca_init_lattice(self.params, spins, stream)
+
+    def sweep(self, T, log=False):
+        return tca_sweep(self.ctx, T, log=log, N=self.N)
+
+    def eigvals(self, sites, Lc=None, proposed=None):
+        return tca_cluster_eigvals(self.ctx, sites, Lc, proposed)
+
+    def observables(self):
+        return tca_observables(self.ctx, self.L)
+
+    def spins(self):
+        return self.observables()[0]
+
+    def set_state(self, spins, sweep_counter):
+        tca_set_state(self.ctx, spins, sweep_counter)
+
+    @property
+    def sweep_counter(self):
+        return tca_get_sweep_counter(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            tca_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

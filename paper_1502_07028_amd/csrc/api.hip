@@ -1,0 +1,443 @@
+// C ABI of libtca.so (declared in include/tca.h): argument checking, device
+// memory owned by a context, and the host-side block schedule of a sweep.
+//
+// A sweep (Sec. II(c), Fig. 2) is issued as the four quadrant blocks of the
+// parallel scheme (Sec. III(a), Fig. 3/4): for each block one batched launch
+// solves every cluster (old and new matrix) and one launch makes the block's
+// Metropolis decisions; the kernel boundary plays the role of the broadcast of
+// the updated spin array between blocks.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace tca;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(const char* fmt, const char* a = "", int line = 0) {
+  snprintf(g_err, sizeof(g_err), fmt, a, line);
+}
+
+#define TCA_CK(expr)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess) {                                            \
+      set_err("HIP error %s at api.hip:%d", hipGetErrorString(e_), __LINE__); \
+      return TCA_E_DEVICE;                                             \
+    }                                                                  \
+  } while (0)
+
+#define TCA_INVAL(msg)        \
+  do {                        \
+    set_err("%s", msg);       \
+    return TCA_E_INVAL;       \
+  } while (0)
+
+bool is_fin(double v) { return isfinite(v) != 0; }
+
+bool unit_spins(const double* s, long n) {
+  for (long p = 0; p < n; ++p) {
+    const double x = s[3 * p], y = s[3 * p + 1], z = s[3 * p + 2];
+    const double r = x * x + y * y + z * z;
+    if (!is_fin(r) || fabs(sqrt(r) - 1.0) > 1e-12) return false;
+  }
+  return true;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t n) { return hipMalloc((void**)&p, n * sizeof(T) + 16); }
+};
+
+}  // namespace
+
+struct tca_ctx {
+  tca_params p;
+  hipStream_t stream = nullptr;
+  int N = 0, h = 0;
+  double* S = nullptr;           // N x 3
+  double* Fpair = nullptr;       // 2 * h*h
+  int32_t* cls_count = nullptr;  // 4
+  int32_t* cls_list = nullptr;   // 4 * h*h
+  unsigned long long* counters = nullptr;  // 4
+  double* sq_work = nullptr;     // 6 N
+  double* sq_out = nullptr;      // N
+  uint64_t sweep_counter = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> prof;  // event pool for TCA_FLAG_PROFILE
+};
+
+// Event pairs bracketing launches when profiling: pairs [2i, 2i+1].
+struct ProfRec {
+  tca_ctx* c;
+  bool on;
+  size_t used = 0;
+  std::vector<int> kind;  // 0 cluster, 1 decide
+  hipError_t begin() {
+    if (!on) return hipSuccess;
+    while (c->prof.size() < 2 * (used + 1)) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      c->prof.push_back(e);
+    }
+    return hipEventRecord(c->prof[2 * used], c->stream);
+  }
+  hipError_t end(int k) {
+    if (!on) return hipSuccess;
+    kind.push_back(k);
+    return hipEventRecord(c->prof[2 * used++ + 1], c->stream);
+  }
+};
+
+static int check_Lc(int Lc, int L) { return Lc >= 2 && Lc <= kMaxLc && Lc <= L / 2 + 1; }
+
+static void free_ctx(tca_ctx* c) {
+  if (!c) return;
+  if (c->S) (void)hipFree(c->S);
+  if (c->Fpair) (void)hipFree(c->Fpair);
+  if (c->cls_count) (void)hipFree(c->cls_count);
+  if (c->cls_list) (void)hipFree(c->cls_list);
+  if (c->counters) (void)hipFree(c->counters);
+  if (c->sq_work) (void)hipFree(c->sq_work);
+  if (c->sq_out) (void)hipFree(c->sq_out);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->prof) (void)hipEventDestroy(e);
+  delete c;
+}
+
+static ModelParams model_of(const tca_ctx* c) {
+  return ModelParams{c->p.t, c->p.JH, c->p.JAF, c->p.mu, c->p.seed};
+}
+
+extern "C" {
+
+const char* tca_strerror(int s) {
+  switch (s) {
+    case TCA_OK: return "ok";
+    case TCA_E_INVAL: return "invalid argument";
+    case TCA_E_NOMEM: return "out of memory";
+    case TCA_E_DEVICE: return "HIP device error";
+    case TCA_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* tca_last_error(void) { return g_err; }
+
+int tca_abi_sizes(int32_t* out3) {
+  if (!out3) return TCA_E_INVAL;
+  out3[0] = (int32_t)sizeof(tca_params);
+  out3[1] = (int32_t)sizeof(tca_update_record);
+  out3[2] = (int32_t)sizeof(tca_sweep_stats);
+  return TCA_OK;
+}
+
+int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_stream,
+                     tca_ctx** out) {
+  g_err[0] = 0;
+  if (!out) TCA_INVAL("out is NULL");
+  *out = nullptr;
+  if (!p) TCA_INVAL("params is NULL");
+  if (p->abi_version != TCA_ABI_VERSION) TCA_INVAL("abi_version mismatch");
+  if (p->L < 2 || (p->L & 1) || p->L > 4096) TCA_INVAL("L must be even, 2 <= L <= 4096");
+  if (p->n_classes < 0 || p->n_classes > 4) TCA_INVAL("n_classes must be 0..4");
+  if (p->n_classes == 0 && !check_Lc(p->Lc, p->L))
+    TCA_INVAL("Lc must satisfy 2 <= Lc <= min(10, L/2+1)");
+  for (int k = 0; k < p->n_classes; ++k)
+    if (!check_Lc(p->Lc_classes[k], p->L))
+      TCA_INVAL("every size class must satisfy 2 <= Lc <= min(10, L/2+1)");
+  if (p->precision != TCA_FP64 && p->precision != TCA_MIXED) TCA_INVAL("bad precision");
+  if (p->init < TCA_INIT_RANDOM || p->init > TCA_INIT_USER) TCA_INVAL("bad init");
+  if (p->flags & ~TCA_FLAG_PROFILE) TCA_INVAL("unknown flag bits");
+  if (!is_fin(p->t) || !is_fin(p->JH) || !is_fin(p->JAF) || !is_fin(p->mu))
+    TCA_INVAL("model parameters must be finite");
+  const int N = p->L * p->L;
+  if (p->init == TCA_INIT_USER) {
+    if (!spins_xyz) TCA_INVAL("TCA_INIT_USER needs spins_xyz");
+    if (!unit_spins(spins_xyz, N)) TCA_INVAL("spins must have unit norm within 1e-12");
+  }
+  tca_ctx* c = new (std::nothrow) tca_ctx;
+  if (!c) {
+    set_err("host allocation failed");
+    return TCA_E_NOMEM;
+  }
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  c->N = N;
+  c->h = p->L / 2;
+  const size_t hh = (size_t)c->h * c->h;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc((void**)&c->S, sizeof(double) * 3 * N);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->Fpair, sizeof(double) * 2 * hh);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->cls_count, sizeof(int32_t) * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->cls_list, sizeof(int32_t) * 4 * hh);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * 4);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+  if (e != hipSuccess) {
+    set_err("device allocation failed: %s", hipGetErrorString(e));
+    free_ctx(c);
+    return e == hipErrorOutOfMemory ? TCA_E_NOMEM : TCA_E_DEVICE;
+  }
+  if (p->init == TCA_INIT_USER) {
+    e = hipMemcpyAsync(c->S, spins_xyz, sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->stream);
+  } else {
+    e = launch_init_spins(c->S, p->L, p->init, p->seed, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    set_err("initialization failed: %s", hipGetErrorString(e));
+    free_ctx(c);
+    return TCA_E_DEVICE;
+  }
+  *out = c;
+  return TCA_OK;
+}
+
+int tca_destroy(tca_ctx* c) {
+  free_ctx(c);
+  return TCA_OK;
+}
+
+int tca_set_state(tca_ctx* c, const double* spins_xyz, uint64_t sweep_counter) {
+  g_err[0] = 0;
+  if (!c || !spins_xyz) TCA_INVAL("NULL argument");
+  if (!unit_spins(spins_xyz, c->N)) TCA_INVAL("spins must have unit norm within 1e-12");
+  TCA_CK(hipMemcpyAsync(c->S, spins_xyz, sizeof(double) * 3 * c->N, hipMemcpyHostToDevice,
+                        c->stream));
+  TCA_CK(hipStreamSynchronize(c->stream));
+  c->sweep_counter = sweep_counter;
+  return TCA_OK;
+}
+
+int tca_get_sweep_counter(tca_ctx* c, uint64_t* sc) {
+  g_err[0] = 0;
+  if (!c || !sc) TCA_INVAL("NULL argument");
+  *sc = c->sweep_counter;
+  return TCA_OK;
+}
+
+int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* log,
+              tca_sweep_stats* st) {
+  g_err[0] = 0;
+  if (!c || !T) TCA_INVAL("NULL argument");
+  if (nsweeps < 0) TCA_INVAL("nsweeps < 0");
+  for (int s = 0; s < nsweeps; ++s)
+    if (!is_fin(T[s]) || T[s] <= 0.0) TCA_INVAL("temperatures must be finite and > 0");
+  const int L = c->p.L, h = c->h, hh = h * h;
+  DevBuf<tca_update_record> dlog;
+  if (log && nsweeps > 0) {
+    hipError_t e = dlog.alloc((size_t)nsweeps * c->N);
+    if (e != hipSuccess) {
+      set_err("log allocation failed: %s", hipGetErrorString(e));
+      return TCA_E_NOMEM;
+    }
+  }
+  const ModelParams m = model_of(c);
+  ProfRec pr{c, (c->p.flags & TCA_FLAG_PROFILE) != 0};
+  TCA_CK(launch_zero_u64(c->counters, 4, c->stream));
+  TCA_CK(hipEventRecord(c->ev0, c->stream));
+  for (int s = 0; s < nsweeps; ++s) {
+    const uint64_t sweep = c->sweep_counter + (uint64_t)s;
+    for (int K = 0; K < 4; ++K) {
+      const BlockGeom g{L, h, h * (K & 1), h * (K >> 1)};
+      TCA_CK(pr.begin());
+      if (c->p.n_classes == 0) {
+        TCA_CK(launch_cluster_block(c->p.precision, c->p.Lc, c->S, g, m, sweep, T[s], nullptr,
+                                    nullptr, hh, c->Fpair, c->stream));
+      } else {
+        const ClassLists cl{c->cls_count, c->cls_list};
+        TCA_CK(launch_classify(c->p.Lc_classes, c->p.n_classes, g, c->p.seed, sweep, cl,
+                               c->stream));
+        // largest clusters first so the longest workgroups start earliest
+        int order[4] = {0, 1, 2, 3};
+        for (int a = 0; a < c->p.n_classes; ++a)
+          for (int b = a + 1; b < c->p.n_classes; ++b)
+            if (c->p.Lc_classes[order[b]] > c->p.Lc_classes[order[a]]) {
+              const int tmp = order[a];
+              order[a] = order[b];
+              order[b] = tmp;
+            }
+        for (int a = 0; a < c->p.n_classes; ++a) {
+          const int k = order[a];
+          TCA_CK(launch_cluster_block(c->p.precision, c->p.Lc_classes[k], c->S, g, m, sweep, T[s],
+                                      c->cls_list + (size_t)k * hh, c->cls_count + k, hh,
+                                      c->Fpair, c->stream));
+        }
+      }
+      TCA_CK(pr.end(0));
+      TCA_CK(pr.begin());
+      TCA_CK(launch_decide(c->S, c->Fpair, g, m, sweep, T[s], c->p.Lc, c->p.Lc_classes,
+                           c->p.n_classes, K, dlog.p ? dlog.p + (size_t)s * c->N : nullptr,
+                           c->counters, c->stream));
+      TCA_CK(pr.end(1));
+    }
+  }
+  TCA_CK(hipEventRecord(c->ev1, c->stream));
+  TCA_CK(hipStreamSynchronize(c->stream));
+  c->sweep_counter += (uint64_t)nsweeps;
+  if (log && nsweeps > 0)
+    TCA_CK(hipMemcpy(log, dlog.p, sizeof(tca_update_record) * (size_t)nsweeps * c->N,
+                     hipMemcpyDeviceToHost));
+  if (st) {
+    unsigned long long cnt[4];
+    TCA_CK(hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    TCA_CK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    st->accepted = (int64_t)cnt[0];
+    st->near_threshold = (int64_t)cnt[1];
+    st->updates = (int64_t)cnt[2];
+    st->elapsed_ms = ms;
+    st->cluster_ms = st->decide_ms = 0.0;
+    st->cluster_launches = st->decide_launches = 0;
+    for (size_t i = 0; i < pr.used; ++i) {
+      float e = 0.f;
+      TCA_CK(hipEventElapsedTime(&e, c->prof[2 * i], c->prof[2 * i + 1]));
+      if (pr.kind[i] == 0) {
+        st->cluster_ms += e;
+        st->cluster_launches += 1;
+      } else {
+        st->decide_ms += e;
+        st->decide_launches += 1;
+      }
+    }
+  }
+  return TCA_OK;
+}
+
+int tca_cluster_eigvals(tca_ctx* c, const int32_t* sites, const int32_t* Lc,
+                        const double* proposed_xyz, int32_t count, double* eig, int32_t ld) {
+  g_err[0] = 0;
+  if (!c || !sites || !eig) TCA_INVAL("NULL argument");
+  if (count < 0) TCA_INVAL("count < 0");
+  if (count == 0) return TCA_OK;
+  const int L = c->p.L;
+  std::vector<int> lcs(count);
+  for (int r = 0; r < count; ++r) {
+    if (sites[r] < 0 || sites[r] >= c->N) TCA_INVAL("site out of range");
+    lcs[r] = Lc ? Lc[r] : c->p.Lc;
+    if (!check_Lc(lcs[r], L)) TCA_INVAL("cluster size out of range");
+    if (ld < 2 * lcs[r] * lcs[r]) TCA_INVAL("ld < 2*Lc^2");
+  }
+  if (proposed_xyz && !unit_spins(proposed_xyz, count))
+    TCA_INVAL("proposed spins must have unit norm within 1e-12");
+  DevBuf<int32_t> dsites;
+  DevBuf<double> dprop, dev;
+  TCA_CK(dsites.alloc(count));
+  TCA_CK(dprop.alloc((size_t)3 * count));
+  TCA_CK(dev.alloc((size_t)count * ld));
+  const ModelParams m = model_of(c);
+  std::vector<int32_t> hs(count);
+  std::vector<double> hp(3 * (size_t)count);
+  for (int Lv = 2; Lv <= kMaxLc; ++Lv) {
+    int k = 0;
+    std::vector<int> rows;
+    for (int r = 0; r < count; ++r)
+      if (lcs[r] == Lv) {
+        rows.push_back(r);
+        hs[k] = sites[r];
+        if (proposed_xyz)
+          for (int a = 0; a < 3; ++a) hp[3 * k + a] = proposed_xyz[3 * r + a];
+        ++k;
+      }
+    if (k == 0) continue;
+    TCA_CK(hipMemcpy(dsites.p, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice));
+    if (proposed_xyz)
+      TCA_CK(hipMemcpy(dprop.p, hp.data(), sizeof(double) * 3 * k, hipMemcpyHostToDevice));
+    TCA_CK(launch_cluster_eig(c->p.precision, Lv, c->S, L, m, dsites.p,
+                              proposed_xyz ? dprop.p : nullptr, k, dev.p, ld, c->stream));
+    TCA_CK(hipStreamSynchronize(c->stream));
+    std::vector<double> tmp((size_t)k * ld);
+    TCA_CK(hipMemcpy(tmp.data(), dev.p, sizeof(double) * k * ld, hipMemcpyDeviceToHost));
+    for (int q = 0; q < k; ++q)
+      memcpy(eig + (size_t)rows[q] * ld, tmp.data() + (size_t)q * ld,
+             sizeof(double) * 2 * Lv * Lv);
+  }
+  return TCA_OK;
+}
+
+int tca_observables(tca_ctx* c, double* spins_out, double* Sq, double* m) {
+  g_err[0] = 0;
+  if (!c) TCA_INVAL("NULL context");
+  const int N = c->N, L = c->p.L;
+  if (Sq) {
+    if (!c->sq_work) TCA_CK(hipMalloc((void**)&c->sq_work, sizeof(double) * 6 * N));
+    if (!c->sq_out) TCA_CK(hipMalloc((void**)&c->sq_out, sizeof(double) * N));
+    TCA_CK(launch_sq(c->S, L, c->sq_work, c->sq_out, c->stream));
+  }
+  TCA_CK(hipStreamSynchronize(c->stream));
+  if (Sq) TCA_CK(hipMemcpy(Sq, c->sq_out, sizeof(double) * N, hipMemcpyDeviceToHost));
+  if (spins_out || m) {
+    std::vector<double> tmp;
+    double* dst = spins_out;
+    if (!dst) {
+      tmp.resize(3 * (size_t)N);
+      dst = tmp.data();
+    }
+    TCA_CK(hipMemcpy(dst, c->S, sizeof(double) * 3 * N, hipMemcpyDeviceToHost));
+    if (m) {
+      double a[3] = {0, 0, 0};
+      for (int p = 0; p < N; ++p)
+        for (int k = 0; k < 3; ++k) a[k] += dst[3 * p + k];
+      for (int k = 0; k < 3; ++k) m[k] = a[k] / N;
+    }
+  }
+  return TCA_OK;
+}
+
+static int heevals_checks(const double* A, int32_t n, int32_t batch, int32_t precision) {
+  if (!A) TCA_INVAL("A is NULL");
+  if (!supported_n(n)) TCA_INVAL("n must satisfy 2 <= n <= 200");
+  if (batch < 0) TCA_INVAL("batch < 0");
+  if (precision != TCA_FP64 && precision != TCA_MIXED) TCA_INVAL("bad precision");
+  return TCA_OK;
+}
+
+int tca_heevals_batched_dev(const double* A, int32_t n, int32_t batch, int32_t precision,
+                            double T, double mu, double* w, double* F, void* hip_stream) {
+  g_err[0] = 0;
+  int s = heevals_checks(A, n, batch, precision);
+  if (s != TCA_OK) return s;
+  if (F && (!is_fin(T) || T <= 0.0 || !is_fin(mu))) TCA_INVAL("T must be > 0 and mu finite");
+  if (batch == 0) return TCA_OK;
+  TCA_CK(launch_heevals(precision, n, A, batch, T, mu, w, F, (hipStream_t)hip_stream));
+  return TCA_OK;
+}
+
+int tca_heevals_batched(const double* A, int32_t n, int32_t batch, int32_t precision, double T,
+                        double mu, double* w, double* F) {
+  g_err[0] = 0;
+  int s = heevals_checks(A, n, batch, precision);
+  if (s != TCA_OK) return s;
+  if (!w && !F) TCA_INVAL("w and F are both NULL");
+  if (F && (!is_fin(T) || T <= 0.0 || !is_fin(mu))) TCA_INVAL("T must be > 0 and mu finite");
+  if (batch == 0) return TCA_OK;
+  const size_t nA = (size_t)batch * n * n * 2;
+  DevBuf<double> dA, dw, dF;
+  TCA_CK(dA.alloc(nA));
+  TCA_CK(dw.alloc((size_t)batch * n));
+  TCA_CK(dF.alloc((size_t)batch));
+  TCA_CK(hipMemcpy(dA.p, A, sizeof(double) * nA, hipMemcpyHostToDevice));
+  TCA_CK(launch_heevals(precision, n, dA.p, batch, T, mu, w ? dw.p : nullptr, F ? dF.p : nullptr,
+                        nullptr));
+  TCA_CK(hipDeviceSynchronize());
+  if (w) TCA_CK(hipMemcpy(w, dw.p, sizeof(double) * batch * n, hipMemcpyDeviceToHost));
+  if (F) TCA_CK(hipMemcpy(F, dF.p, sizeof(double) * batch, hipMemcpyDeviceToHost));
+  return TCA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,306 @@
+// Eigenvalues and fermionic free energy of one dense complex Hermitian matrix
+// per workgroup, the matrix held in registers.
+//
+// The paper diagonalizes every traveling-cluster Hamiltonian exactly
+// (Sec. II(b); Fig. 2 steps (b), (d)) at a cost ~ (matrix dimension)^3.  Here a
+// workgroup of G x G threads reduces the matrix to real symmetric tridiagonal
+// form with complex Householder reflectors (unblocked, one column per step),
+// then finds every eigenvalue by Sturm-count bisection in FP64 and sums the
+// grand potential  F = sum_i [min(x_i,0) - T log1p(exp(-|x_i|/T))],
+// x_i = eps_i - mu,  in FP64.
+//
+// Data layout.  Element (i, j) of the n x n matrix lives in thread
+// (tr, tc) = (i mod G, j mod G), local block (li, lj) = (i / G, j / G); only the
+// lower triangle is stored (li >= lj, and inside a diagonal local block only
+// tr >= tc carries data, the rest stays zero).  A thread therefore holds
+// LR(LR+1)/2 complex numbers, LR = ceil(n/G), and the whole matrix never leaves
+// the register file.  Vectors of each step (current column, reflector, A*v)
+// are exchanged through LDS.
+//
+// One reduction step k (trailing block B = A[k+1:, k+1:], column x = A[k+1:, k]):
+//   reflector   beta = -sign(Re x_0) ||x||, tau = (beta - x_0)/beta,
+//               v = (1, x_1.. / (x_0 - beta)), so (I - tau v v^H)^H x = beta e_1
+//   y = B v                  (row partials + column partials, summed in LDS)
+//   w = tau y - (|tau|^2/2) Re(v^H y) v
+//   B <- B - v w^H - w v^H   (the two-sided update H^H B H)
+// and beta becomes the off-diagonal e_k (only e_k^2 enters the eigenvalues).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <float.h>
+#include <stdint.h>
+
+namespace tca {
+
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int G, int LR, typename R>
+struct Solver {
+  static constexpr int NT = G * G;            // threads per workgroup
+  static constexpr int NW = NT / 64;          // wavefronts per workgroup
+  static constexpr int NP = G * LR;           // padded dimension
+  static constexpr int NLOC = LR * (LR + 1) / 2;
+  static constexpr int PITCH = NP + 1;        // LDS row pitch of partial sums
+  static_assert(NT % 64 == 0, "workgroup must be whole wavefronts");
+
+  struct Smem {
+    cx<R> x[2][NP];      // current column (double-buffered)
+    cx<R> y[NP];         // B v
+    cx<R> pr[G * PITCH]; // row partials   [tc][i]
+    cx<R> pc[G * PITCH]; // column partials [tr][j]
+    double d[NP];        // tridiagonal diagonal
+    double e2[NP];       // squared off-diagonal
+    double ea[NP];       // |off-diagonal|
+    double ev[NP];       // eigenvalues, ascending
+    double red[NW];
+  };
+
+  static __device__ __forceinline__ constexpr int idx(int li, int lj) { return li * (li + 1) / 2 + lj; }
+
+  // Copy column k (rows k+1..n-1) of the register matrix to LDS; also write
+  // the diagonal entry d[k] and, at the last column, the final 2x2 entries.
+  static __device__ __forceinline__ void write_col(int n, int k, const cx<R> (&A)[NLOC],
+                                                   cx<R>* xb, Smem& sm) {
+    const int tid = threadIdx.x, tr = tid / G, tc = tid % G;
+    const int kb = k / G, kc = k % G;
+#pragma unroll
+    for (int li = 0; li < LR; ++li) {
+#pragma unroll
+      for (int lj = 0; lj <= li; ++lj) {
+        if (lj == kb && tc == kc) {
+          const int i = tr + G * li;
+          const cx<R> a = A[idx(li, lj)];
+          if (i > k && i < n) xb[i] = a;
+          if (i == k) sm.d[k] = (double)a.re;
+          if (k == n - 2 && i == n - 1) {
+            const double ar = (double)a.re, ai = (double)a.im;
+            sm.e2[k] = ar * ar + ai * ai;
+            sm.ea[k] = sqrt(ar * ar + ai * ai);
+          }
+        }
+        if (k == n - 2 && lj == (n - 1) / G && li == lj && tr == (n - 1) % G && tc == (n - 1) % G)
+          sm.d[n - 1] = (double)A[idx(li, lj)].re;
+      }
+    }
+  }
+
+  // Householder reduction to (d, e2); leaves them in LDS.
+  static __device__ void tridiagonalize(const int n, cx<R> (&A)[NLOC], Smem& sm) {
+    const int tid = threadIdx.x, tr = tid / G, tc = tid % G, lane = tid & 63;
+    if (n == 1) {
+      if (tid == 0) sm.d[0] = (double)A[0].re;
+      __syncthreads();
+      return;
+    }
+    write_col(n, 0, A, sm.x[0], sm);
+    __syncthreads();
+    int buf = 0;
+    for (int k = 0; k < n - 2; ++k) {
+      const cx<R>* xk = sm.x[buf];
+      // ---- reflector, computed redundantly and identically by every wavefront
+      R s2 = R(0);
+      for (int i = k + 2 + lane; i < n; i += 64) {
+        const cx<R> v = xk[i];
+        s2 += v.re * v.re + v.im * v.im;
+      }
+      s2 = wave_sum(s2);
+      const cx<R> al = xk[k + 1];
+      R beta, tre, tim, scr, sci;
+      if (s2 == R(0) && al.im == R(0)) {
+        beta = al.re;
+        tre = tim = scr = sci = R(0);
+      } else {
+        const R nrm = sqrt(al.re * al.re + al.im * al.im + s2);
+        beta = al.re >= R(0) ? -nrm : nrm;
+        tre = (beta - al.re) / beta;
+        tim = -al.im / beta;
+        const R dr = al.re - beta, di = al.im, den = dr * dr + di * di;
+        scr = dr / den;
+        sci = -di / den;
+      }
+      if (tid == 0) {
+        sm.e2[k] = (double)beta * (double)beta;
+        sm.ea[k] = fabs((double)beta);
+      }
+      auto vget = [&](int i) -> cx<R> {
+        if (i == k + 1) return {R(1), R(0)};
+        if (i > k + 1 && i < n) {
+          const cx<R> v = xk[i];
+          return {v.re * scr - v.im * sci, v.re * sci + v.im * scr};
+        }
+        return {R(0), R(0)};
+      };
+      const int kb = (k + 1) / G;
+      // ---- y = B v : row partials (lower part) and column partials (upper part)
+      cx<R> vc[LR], yc[LR];
+#pragma unroll
+      for (int lj = 0; lj < LR; ++lj) {
+        vc[lj] = {R(0), R(0)};
+        yc[lj] = {R(0), R(0)};
+        if (lj >= kb) vc[lj] = vget(tc + G * lj);
+      }
+      const R ms = (tr > tc) ? R(1) : R(0);
+#pragma unroll
+      for (int li = 0; li < LR; ++li) {
+        if (li < kb) continue;
+        const int i = tr + G * li;
+        const cx<R> vi = vget(i);
+        cx<R> yr = {R(0), R(0)};
+#pragma unroll
+        for (int lj = 0; lj < li; ++lj) {
+          if (lj < kb) continue;
+          const cx<R> a = A[idx(li, lj)];
+          yr.re += a.re * vc[lj].re - a.im * vc[lj].im;
+          yr.im += a.re * vc[lj].im + a.im * vc[lj].re;
+          yc[lj].re += a.re * vi.re + a.im * vi.im;
+          yc[lj].im += a.re * vi.im - a.im * vi.re;
+        }
+        {
+          const cx<R> a = A[idx(li, li)];
+          yr.re += a.re * vc[li].re - a.im * vc[li].im;
+          yr.im += a.re * vc[li].im + a.im * vc[li].re;
+          yc[li].re += ms * (a.re * vi.re + a.im * vi.im);
+          yc[li].im += ms * (a.re * vi.im - a.im * vi.re);
+        }
+        if (i > k && i < n) sm.pr[tc * PITCH + i] = yr;
+      }
+#pragma unroll
+      for (int lj = 0; lj < LR; ++lj) {
+        const int j = tc + G * lj;
+        if (lj >= kb && j > k && j < n) sm.pc[tr * PITCH + j] = yc[lj];
+      }
+      __syncthreads();
+      for (int i = k + 1 + tid; i < n; i += NT) {
+        cx<R> s = {R(0), R(0)};
+#pragma unroll 4
+        for (int t = 0; t < G; ++t) {
+          const cx<R> a = sm.pr[t * PITCH + i], b = sm.pc[t * PITCH + i];
+          s.re += a.re + b.re;
+          s.im += a.im + b.im;
+        }
+        sm.y[i] = s;
+      }
+      __syncthreads();
+      // ---- w = tau y - (|tau|^2/2) Re(v^H y) v
+      R c = R(0);
+      for (int i = k + 1 + lane; i < n; i += 64) {
+        const cx<R> v = vget(i), yy = sm.y[i];
+        c += v.re * yy.re + v.im * yy.im;
+      }
+      c = wave_sum(c);
+      const R a2 = R(0.5) * (tre * tre + tim * tim) * c;
+      auto wget = [&](int i, cx<R> v) -> cx<R> {
+        if (i <= k || i >= n) return {R(0), R(0)};
+        const cx<R> yy = sm.y[i];
+        return {tre * yy.re - tim * yy.im - a2 * v.re, tre * yy.im + tim * yy.re - a2 * v.im};
+      };
+      cx<R> wc[LR];
+#pragma unroll
+      for (int lj = 0; lj < LR; ++lj) {
+        wc[lj] = {R(0), R(0)};
+        if (lj >= kb) wc[lj] = wget(tc + G * lj, vc[lj]);
+      }
+      // ---- B <- B - v w^H - w v^H on the stored lower triangle
+      const R mr = (tr >= tc) ? R(1) : R(0);
+#pragma unroll
+      for (int li = 0; li < LR; ++li) {
+        if (li < kb) continue;
+        const int i = tr + G * li;
+        const cx<R> vi = vget(i);
+        const cx<R> wi = wget(i, vi);
+#pragma unroll
+        for (int lj = 0; lj < li; ++lj) {
+          if (lj < kb) continue;
+          cx<R>& a = A[idx(li, lj)];
+          a.re -= vi.re * wc[lj].re + vi.im * wc[lj].im + wi.re * vc[lj].re + wi.im * vc[lj].im;
+          a.im -= vi.im * wc[lj].re - vi.re * wc[lj].im + wi.im * vc[lj].re - wi.re * vc[lj].im;
+        }
+        {
+          cx<R>& a = A[idx(li, li)];
+          const R ur = vi.re * wc[li].re + vi.im * wc[li].im + wi.re * vc[li].re + wi.im * vc[li].im;
+          const R ui = vi.im * wc[li].re - vi.re * wc[li].im + wi.im * vc[li].re - wi.re * vc[li].im;
+          a.re -= mr * ur;
+          a.im -= ms * ui;
+        }
+      }
+      write_col(n, k + 1, A, sm.x[buf ^ 1], sm);
+      buf ^= 1;
+      __syncthreads();
+    }
+  }
+
+  // Number of eigenvalues of the tridiagonal (d, e2) below x (Sturm count of
+  // the LDL^T pivots, with tiny pivots replaced by -pivmin).
+  static __device__ __forceinline__ int sturm(const int n, const double x, const double* d,
+                                              const double* e2, const double pivmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int c = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+      q = (d[i] - x) - e2[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
+    return c;
+  }
+
+  // All eigenvalues by bisection (FP64), ascending, into sm.ev.
+  static __device__ void eigenvalues(const int n, Smem& sm) {
+    const int tid = threadIdx.x;
+    double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? sm.ea[i - 1] : 0.0) + (i < n - 1 ? sm.ea[i] : 0.0);
+      lo = fmin(lo, sm.d[i] - r);
+      hi = fmax(hi, sm.d[i] + r);
+      if (i < n - 1) emax2 = fmax(emax2, sm.e2[i]);
+    }
+    const double pivmin = DBL_MIN * fmax(1.0, emax2);
+    const double span = fmax(fabs(lo), fabs(hi));
+    const double widen = 2.0 * DBL_EPSILON * span * (double)n + pivmin;
+    lo -= widen;
+    hi += widen;
+    const double tol = 2.0 * DBL_EPSILON * span + pivmin;
+    for (int j = tid; j < n; j += NT) {
+      double a = lo, b = hi;
+      while (b - a > tol) {
+        const double mid = 0.5 * (a + b);
+        if (mid <= a || mid >= b) break;
+        if (sturm(n, mid, sm.d, sm.e2, pivmin) > j)
+          b = mid;
+        else
+          a = mid;
+      }
+      sm.ev[j] = 0.5 * (a + b);
+    }
+    __syncthreads();
+  }
+
+  // F = sum_i [min(x,0) - T log1p(exp(-|x|/T))], x = ev_i - mu (FP64), result
+  // valid in thread 0; fixed reduction order.
+  static __device__ double free_energy(const int n, const double T, const double mu, Smem& sm) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double acc = 0.0;
+    for (int j = tid; j < n; j += NT) {
+      const double x = sm.ev[j] - mu;
+      acc += fmin(x, 0.0) - T * log1p(exp(-fabs(x) / T));
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sm.red[wave] = acc;
+    __syncthreads();
+    double F = 0.0;
+    if (tid == 0)
+      for (int w = 0; w < NW; ++w) F += sm.red[w];
+    return F;
+  }
+};
+
+}  // namespace tca

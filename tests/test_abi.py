@@ -1,0 +1,90 @@
+"""The C ABI library loads, exports every symbol the header declares, agrees
+with the binding on struct layouts, and rejects bad arguments before any
+device work (these calls need no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tca.h")
+LIB = os.path.join(ROOT, "paper_1502_07028_amd", "libtca.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libtca.so not built (run __graft_entry__.build())")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tca_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_declares_entry_points():
+    fns = header_functions()
+    for name in ["tca_init_lattice", "tca_sweep", "tca_cluster_eigvals", "tca_observables",
+                 "tca_heevals_batched", "tca_destroy", "tca_strerror"]:
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [f for f in header_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match():
+    import paper_1502_07028_amd as tca
+    assert tca.tca_abi_sizes() == (ctypes.sizeof(tca.tca_params), ctypes.sizeof(tca.tca_update_record),
+                                   ctypes.sizeof(tca.tca_sweep_stats))
+    assert ctypes.sizeof(tca.tca_update_record) == 32
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(L=7, Lc=3), "even"),
+    (dict(L=8, Lc=6), "Lc"),
+    (dict(L=8, Lc=1), "Lc"),
+    (dict(L=40, Lc=11), "Lc"),
+    (dict(L=8, Lc=4, precision=5), "precision"),
+    (dict(L=8, Lc=4, Lc_classes=(4, 6)), "size class"),
+    (dict(L=8, Lc=4, JH=float("nan")), "finite"),
+    (dict(L=8, Lc=4, flags=6), "flag"),
+])
+def test_init_rejects_bad_params(kw, msg):
+    import paper_1502_07028_amd as tca
+    p = tca.make_params(**kw)
+    with pytest.raises(tca.TCAError) as e:
+        tca.tca_init_lattice(p)
+    assert e.value.status == tca.TCA_E_INVAL
+    assert msg in str(e.value)
+
+
+def test_init_rejects_non_unit_user_spins():
+    import paper_1502_07028_amd as tca
+    p = tca.make_params(L=4, Lc=2, init=tca.TCA_INIT_USER)
+    spins = np.tile([0.0, 0.0, 1.0 + 1e-9], (16, 1))
+    with pytest.raises(tca.TCAError) as e:
+        tca.tca_init_lattice(p, spins)
+    assert e.value.status == tca.TCA_E_INVAL
+
+
+def test_heevals_rejects_bad_sizes():
+    import paper_1502_07028_amd as tca
+    with pytest.raises(tca.TCAError) as e:
+        tca.tca_heevals_batched(np.zeros((1, 201, 201), complex))
+    assert e.value.status == tca.TCA_E_INVAL
+    with pytest.raises(tca.TCAError):
+        tca.tca_heevals_batched(np.zeros((1, 8, 8), complex), precision=3)
+
+
+def test_strerror_and_abi_version():
+    lib = ctypes.CDLL(LIB)
+    lib.tca_strerror.restype = ctypes.c_char_p
+    assert lib.tca_strerror(0) == b"ok"
+    assert lib.tca_strerror(-1) == b"invalid argument"
+    import paper_1502_07028_amd as tca
+    p = tca.make_params(L=8, Lc=4)
+    p.abi_version = 99
+    with pytest.raises(tca.TCAError):
+        tca.tca_init_lattice(p)
