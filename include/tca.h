@@ -86,12 +86,15 @@ typedef struct {
   int64_t accepted;
   int64_t near_threshold;
   double elapsed_ms;        /* device time of the sweeps (HIP events) */
-  /* filled only with TCA_FLAG_PROFILE (else 0): summed durations of the
-   * cluster-solve launches (one per block, or one per size class and block)
-   * and of the decision launches, and their counts */
-  double cluster_ms;
+  /* filled only with TCA_FLAG_PROFILE (else 0): summed durations and counts
+   * of the per-block phases -- Householder reductions of all cluster matrices
+   * of a block (one launch, or one per size class, timed together),
+   * tridiagonal eigenvalues + free energies, and Metropolis decisions */
+  double reduce_ms;
+  double eig_ms;
   double decide_ms;
-  int64_t cluster_launches;
+  int64_t reduce_launches;
+  int64_t eig_launches;
   int64_t decide_launches;
 } tca_sweep_stats;
 

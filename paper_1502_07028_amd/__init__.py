@@ -43,8 +43,9 @@ class tca_update_record(ctypes.Structure):
 class tca_sweep_stats(ctypes.Structure):
     _fields_ = [("updates", ctypes.c_int64), ("accepted", ctypes.c_int64),
                 ("near_threshold", ctypes.c_int64), ("elapsed_ms", ctypes.c_double),
-                ("cluster_ms", ctypes.c_double), ("decide_ms", ctypes.c_double),
-                ("cluster_launches", ctypes.c_int64), ("decide_launches", ctypes.c_int64)]
+                ("reduce_ms", ctypes.c_double), ("eig_ms", ctypes.c_double),
+                ("decide_ms", ctypes.c_double), ("reduce_launches", ctypes.c_int64),
+                ("eig_launches", ctypes.c_int64), ("decide_launches", ctypes.c_int64)]
 
 
 RECORD_DTYPE = np.dtype([("site", "<i4"), ("Lc", "<i2"), ("accept", "u1"), ("flags", "u1"),
@@ -151,8 +152,9 @@ def tca_sweep(ctx, T, nsweeps=None, log=False, N=None):
                           ctypes.byref(st)), "tca_sweep")
     return recs, dict(updates=st.updates, accepted=st.accepted,
                       near_threshold=st.near_threshold, elapsed_ms=st.elapsed_ms,
-                      cluster_ms=st.cluster_ms, decide_ms=st.decide_ms,
-                      cluster_launches=st.cluster_launches, decide_launches=st.decide_launches)
+                      reduce_ms=st.reduce_ms, eig_ms=st.eig_ms, decide_ms=st.decide_ms,
+                      reduce_launches=st.reduce_launches, eig_launches=st.eig_launches,
+                      decide_launches=st.decide_launches)
 
 
 def tca_cluster_eigvals(ctx, sites, Lc=None, proposed=None, ld=None):

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtca.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["kernels.hip", "api.hip"]
+SOURCES = ["cluster_kernels.hip", "sweep_kernels.hip", "api.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # packed FP32 VALU forms stay disabled: plain FP32 code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

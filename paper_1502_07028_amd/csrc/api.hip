@@ -12,6 +12,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -68,7 +70,11 @@ struct tca_ctx {
   hipStream_t stream = nullptr;
   int N = 0, h = 0;
   double* S = nullptr;           // N x 3
-  double* Fpair = nullptr;       // 2 * h*h
+  double* F = nullptr;           // 2 * h*h grand potentials (old, new per cluster)
+  double* D = nullptr;           // 2 * h*h * ld tridiagonal diagonals
+  double* E2 = nullptr;          // 2 * h*h * ld squared off-diagonals
+  int32_t* nmat = nullptr;       // 2 * h*h matrix dimensions
+  int ld = 0;                    // 2 * (largest Lc)^2
   int32_t* cls_count = nullptr;  // 4
   int32_t* cls_list = nullptr;   // 4 * h*h
   unsigned long long* counters = nullptr;  // 4
@@ -84,7 +90,7 @@ struct ProfRec {
   tca_ctx* c;
   bool on;
   size_t used = 0;
-  std::vector<int> kind;  // 0 cluster, 1 decide
+  std::vector<int> kind;  // 0 reduce, 1 eigenvalues, 2 decide
   hipError_t begin() {
     if (!on) return hipSuccess;
     while (c->prof.size() < 2 * (used + 1)) {
@@ -107,7 +113,10 @@ static int check_Lc(int Lc, int L) { return Lc >= 2 && Lc <= kMaxLc && Lc <= L /
 static void free_ctx(tca_ctx* c) {
   if (!c) return;
   if (c->S) (void)hipFree(c->S);
-  if (c->Fpair) (void)hipFree(c->Fpair);
+  if (c->F) (void)hipFree(c->F);
+  if (c->D) (void)hipFree(c->D);
+  if (c->E2) (void)hipFree(c->E2);
+  if (c->nmat) (void)hipFree(c->nmat);
   if (c->cls_count) (void)hipFree(c->cls_count);
   if (c->cls_list) (void)hipFree(c->cls_list);
   if (c->counters) (void)hipFree(c->counters);
@@ -182,7 +191,13 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
   const size_t hh = (size_t)c->h * c->h;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = hipMalloc((void**)&c->S, sizeof(double) * 3 * N);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->Fpair, sizeof(double) * 2 * hh);
+  int maxLc = p->Lc;
+  for (int k = 0; k < p->n_classes; ++k) maxLc = k == 0 ? p->Lc_classes[0] : std::max(maxLc, p->Lc_classes[k]);
+  c->ld = 2 * maxLc * maxLc;
+  if (e == hipSuccess) e = hipMalloc((void**)&c->F, sizeof(double) * 2 * hh);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->D, sizeof(double) * 2 * hh * c->ld);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->E2, sizeof(double) * 2 * hh * c->ld);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->nmat, sizeof(int32_t) * 2 * hh);
   if (e == hipSuccess) e = hipMalloc((void**)&c->cls_count, sizeof(int32_t) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&c->cls_list, sizeof(int32_t) * 4 * hh);
   if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * 4);
@@ -255,10 +270,11 @@ int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* l
     const uint64_t sweep = c->sweep_counter + (uint64_t)s;
     for (int K = 0; K < 4; ++K) {
       const BlockGeom g{L, h, h * (K & 1), h * (K >> 1)};
+      const ReduceOut ro{c->D, c->E2, c->ld, c->nmat};
       TCA_CK(pr.begin());
       if (c->p.n_classes == 0) {
-        TCA_CK(launch_cluster_block(c->p.precision, c->p.Lc, c->S, g, m, sweep, T[s], nullptr,
-                                    nullptr, hh, c->Fpair, c->stream));
+        TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc, c->S, g, m, sweep, nullptr,
+                                           nullptr, hh, ro, c->stream));
       } else {
         const ClassLists cl{c->cls_count, c->cls_list};
         TCA_CK(launch_classify(c->p.Lc_classes, c->p.n_classes, g, c->p.seed, sweep, cl,
@@ -267,24 +283,23 @@ int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* l
         int order[4] = {0, 1, 2, 3};
         for (int a = 0; a < c->p.n_classes; ++a)
           for (int b = a + 1; b < c->p.n_classes; ++b)
-            if (c->p.Lc_classes[order[b]] > c->p.Lc_classes[order[a]]) {
-              const int tmp = order[a];
-              order[a] = order[b];
-              order[b] = tmp;
-            }
+            if (c->p.Lc_classes[order[b]] > c->p.Lc_classes[order[a]]) std::swap(order[a], order[b]);
         for (int a = 0; a < c->p.n_classes; ++a) {
           const int k = order[a];
-          TCA_CK(launch_cluster_block(c->p.precision, c->p.Lc_classes[k], c->S, g, m, sweep, T[s],
-                                      c->cls_list + (size_t)k * hh, c->cls_count + k, hh,
-                                      c->Fpair, c->stream));
+          TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc_classes[k], c->S, g, m, sweep,
+                                             c->cls_list + (size_t)k * hh, c->cls_count + k, hh,
+                                             ro, c->stream));
         }
       }
       TCA_CK(pr.end(0));
       TCA_CK(pr.begin());
-      TCA_CK(launch_decide(c->S, c->Fpair, g, m, sweep, T[s], c->p.Lc, c->p.Lc_classes,
+      TCA_CK(launch_tridiag_eig(c->ld, 2 * hh, ro, T[s], c->p.mu, c->F, nullptr, 0, c->stream));
+      TCA_CK(pr.end(1));
+      TCA_CK(pr.begin());
+      TCA_CK(launch_decide(c->S, c->F, g, m, sweep, T[s], c->p.Lc, c->p.Lc_classes,
                            c->p.n_classes, K, dlog.p ? dlog.p + (size_t)s * c->N : nullptr,
                            c->counters, c->stream));
-      TCA_CK(pr.end(1));
+      TCA_CK(pr.end(2));
     }
   }
   TCA_CK(hipEventRecord(c->ev1, c->stream));
@@ -302,14 +317,17 @@ int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* l
     st->near_threshold = (int64_t)cnt[1];
     st->updates = (int64_t)cnt[2];
     st->elapsed_ms = ms;
-    st->cluster_ms = st->decide_ms = 0.0;
-    st->cluster_launches = st->decide_launches = 0;
+    st->reduce_ms = st->eig_ms = st->decide_ms = 0.0;
+    st->reduce_launches = st->eig_launches = st->decide_launches = 0;
     for (size_t i = 0; i < pr.used; ++i) {
       float e = 0.f;
       TCA_CK(hipEventElapsedTime(&e, c->prof[2 * i], c->prof[2 * i + 1]));
       if (pr.kind[i] == 0) {
-        st->cluster_ms += e;
-        st->cluster_launches += 1;
+        st->reduce_ms += e;
+        st->reduce_launches += 1;
+      } else if (pr.kind[i] == 1) {
+        st->eig_ms += e;
+        st->eig_launches += 1;
       } else {
         st->decide_ms += e;
         st->decide_launches += 1;
@@ -335,11 +353,15 @@ int tca_cluster_eigvals(tca_ctx* c, const int32_t* sites, const int32_t* Lc,
   }
   if (proposed_xyz && !unit_spins(proposed_xyz, count))
     TCA_INVAL("proposed spins must have unit norm within 1e-12");
-  DevBuf<int32_t> dsites;
-  DevBuf<double> dprop, dev;
+  DevBuf<int32_t> dsites, dn;
+  DevBuf<double> dprop, dev, dD, dE;
   TCA_CK(dsites.alloc(count));
   TCA_CK(dprop.alloc((size_t)3 * count));
   TCA_CK(dev.alloc((size_t)count * ld));
+  TCA_CK(dD.alloc((size_t)count * kMaxN));
+  TCA_CK(dE.alloc((size_t)count * kMaxN));
+  TCA_CK(dn.alloc((size_t)count));
+  const ReduceOut ro{dD.p, dE.p, kMaxN, dn.p};
   const ModelParams m = model_of(c);
   std::vector<int32_t> hs(count);
   std::vector<double> hp(3 * (size_t)count);
@@ -358,8 +380,9 @@ int tca_cluster_eigvals(tca_ctx* c, const int32_t* sites, const int32_t* Lc,
     TCA_CK(hipMemcpy(dsites.p, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice));
     if (proposed_xyz)
       TCA_CK(hipMemcpy(dprop.p, hp.data(), sizeof(double) * 3 * k, hipMemcpyHostToDevice));
-    TCA_CK(launch_cluster_eig(c->p.precision, Lv, c->S, L, m, dsites.p,
-                              proposed_xyz ? dprop.p : nullptr, k, dev.p, ld, c->stream));
+    TCA_CK(launch_cluster_sites_reduce(c->p.precision, Lv, c->S, L, m, dsites.p,
+                                       proposed_xyz ? dprop.p : nullptr, k, ro, c->stream));
+    TCA_CK(launch_tridiag_eig(2 * Lv * Lv, k, ro, 1.0, 0.0, nullptr, dev.p, ld, c->stream));
     TCA_CK(hipStreamSynchronize(c->stream));
     std::vector<double> tmp((size_t)k * ld);
     TCA_CK(hipMemcpy(tmp.data(), dev.p, sizeof(double) * k * ld, hipMemcpyDeviceToHost));
@@ -407,6 +430,11 @@ static int heevals_checks(const double* A, int32_t n, int32_t batch, int32_t pre
   return TCA_OK;
 }
 
+// Grow-only device workspace of the device-pointer entry point.
+static std::mutex g_ws_mu;
+static double* g_ws = nullptr;
+static size_t g_ws_bytes = 0;
+
 int tca_heevals_batched_dev(const double* A, int32_t n, int32_t batch, int32_t precision,
                             double T, double mu, double* w, double* F, void* hip_stream) {
   g_err[0] = 0;
@@ -414,7 +442,19 @@ int tca_heevals_batched_dev(const double* A, int32_t n, int32_t batch, int32_t p
   if (s != TCA_OK) return s;
   if (F && (!is_fin(T) || T <= 0.0 || !is_fin(mu))) TCA_INVAL("T must be > 0 and mu finite");
   if (batch == 0) return TCA_OK;
-  TCA_CK(launch_heevals(precision, n, A, batch, T, mu, w, F, (hipStream_t)hip_stream));
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  const size_t need = (size_t)batch * (2 * n * sizeof(double) + sizeof(int32_t)) + 256;
+  if (need > g_ws_bytes) {
+    if (g_ws) TCA_CK(hipFree(g_ws));
+    g_ws = nullptr;
+    g_ws_bytes = 0;
+    TCA_CK(hipMalloc((void**)&g_ws, need));
+    g_ws_bytes = need;
+  }
+  const ReduceOut ro{g_ws, g_ws + (size_t)batch * n, n, (int32_t*)(g_ws + (size_t)2 * batch * n)};
+  hipStream_t st = (hipStream_t)hip_stream;
+  TCA_CK(launch_heevals_reduce(precision, n, A, batch, ro, st));
+  TCA_CK(launch_tridiag_eig(n, batch, ro, T, mu, F, w, n, st));
   return TCA_OK;
 }
 
@@ -427,13 +467,19 @@ int tca_heevals_batched(const double* A, int32_t n, int32_t batch, int32_t preci
   if (F && (!is_fin(T) || T <= 0.0 || !is_fin(mu))) TCA_INVAL("T must be > 0 and mu finite");
   if (batch == 0) return TCA_OK;
   const size_t nA = (size_t)batch * n * n * 2;
-  DevBuf<double> dA, dw, dF;
+  DevBuf<double> dA, dw, dF, dD, dE;
+  DevBuf<int32_t> dn;
   TCA_CK(dA.alloc(nA));
   TCA_CK(dw.alloc((size_t)batch * n));
   TCA_CK(dF.alloc((size_t)batch));
+  TCA_CK(dD.alloc((size_t)batch * n));
+  TCA_CK(dE.alloc((size_t)batch * n));
+  TCA_CK(dn.alloc((size_t)batch));
   TCA_CK(hipMemcpy(dA.p, A, sizeof(double) * nA, hipMemcpyHostToDevice));
-  TCA_CK(launch_heevals(precision, n, dA.p, batch, T, mu, w ? dw.p : nullptr, F ? dF.p : nullptr,
-                        nullptr));
+  const ReduceOut ro{dD.p, dE.p, n, dn.p};
+  TCA_CK(launch_heevals_reduce(precision, n, dA.p, batch, ro, nullptr));
+  TCA_CK(launch_tridiag_eig(n, batch, ro, F ? T : 1.0, mu, F ? dF.p : nullptr, w ? dw.p : nullptr,
+                            n, nullptr));
   TCA_CK(hipDeviceSynchronize());
   if (w) TCA_CK(hipMemcpy(w, dw.p, sizeof(double) * batch * n, hipMemcpyDeviceToHost));
   if (F) TCA_CK(hipMemcpy(F, dF.p, sizeof(double) * batch, hipMemcpyDeviceToHost));

@@ -1,4 +1,5 @@
-// Internal interface between the C ABI (api.hip) and the kernels (kernels.hip).
+// Internal interface between the C ABI (api.hip) and the kernels
+// (cluster_kernels.hip, sweep_kernels.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -10,11 +11,12 @@ namespace tca {
 constexpr int kMaxLc = 10;
 constexpr int kMaxN = 2 * kMaxLc * kMaxLc;  // 200
 
-// Which cluster of a block a workgroup pair works on.
+// One parallel block of the sweep: the (L/2) x (L/2) quadrant with origin
+// (x0, y0); cluster c of the block is anchored at (x0 + c % h, y0 + c / h).
 struct BlockGeom {
-  int L;      // lattice size
-  int h;      // block side L/2
-  int x0, y0; // block origin
+  int L;
+  int h;
+  int x0, y0;
 };
 
 struct ModelParams {
@@ -22,24 +24,41 @@ struct ModelParams {
   uint64_t seed;
 };
 
-// Size classes of one block, filled on the device: list[k][*] holds cluster
-// indices (c = i + h*j within the block) whose drawn size is class k.
+// Size classes of one block, filled on the device: list[k][*] holds the
+// cluster indices c whose drawn size is class k.
 struct ClassLists {
-  int32_t* count;   // [4]
-  int32_t* list;    // [4][h*h]
+  int32_t* count;  // [4]
+  int32_t* list;   // [4][h*h]
 };
 
-hipError_t launch_cluster_block(int precision, int Lc, const double* S, BlockGeom g,
-                                ModelParams m, uint64_t sweep, double T, const int32_t* list,
-                                const int32_t* count, int max_clusters, double* Fpair,
-                                hipStream_t st);
+// Tridiagonal output of the reduction kernels: matrix m has diagonal
+// D[m*ld .. m*ld+n), squared off-diagonal E2[m*ld .. m*ld+n-1), n = nmat[m].
+struct ReduceOut {
+  double* D;
+  double* E2;
+  int ld;
+  int32_t* nmat;
+};
 
-hipError_t launch_cluster_eig(int precision, int Lc, const double* S, int L, ModelParams m,
-                              const int32_t* sites, const double* prop, int count, double* ev,
-                              int ld, hipStream_t st);
+bool supported_n(int n);
 
-hipError_t launch_heevals(int precision, int n, const double* A, int batch, double T, double mu,
-                          double* w, double* F, hipStream_t st);
+// matrices 2c (old) and 2c+1 (new, proposal at the corner) of every cluster c
+// of a block (or of the clusters listed for one size class)
+hipError_t launch_cluster_block_reduce(int precision, int Lc, const double* S, BlockGeom g,
+                                       ModelParams m, uint64_t sweep, const int32_t* list,
+                                       const int32_t* count, int max_clusters, ReduceOut out,
+                                       hipStream_t st);
+
+hipError_t launch_cluster_sites_reduce(int precision, int Lc, const double* S, int L,
+                                       ModelParams m, const int32_t* sites, const double* prop,
+                                       int count, ReduceOut out, hipStream_t st);
+
+hipError_t launch_heevals_reduce(int precision, int n, const double* A, int batch, ReduceOut out,
+                                 hipStream_t st);
+
+// eigenvalues (optional) and grand potential F (optional) of nmats tridiagonals
+hipError_t launch_tridiag_eig(int nmax, int nmats, ReduceOut in, double T, double mu, double* F,
+                              double* ev, int ev_ld, hipStream_t st);
 
 hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g, uint64_t seed,
                            uint64_t sweep, ClassLists cl, hipStream_t st);
@@ -55,7 +74,5 @@ hipError_t launch_sq(const double* S, int L, double* work /* L*L*6 */, double* S
                      hipStream_t st);
 
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
-
-bool supported_n(int n);
 
 }  // namespace tca

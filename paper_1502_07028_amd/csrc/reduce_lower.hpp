@@ -1,40 +1,23 @@
-// Eigenvalues and fermionic free energy of one dense complex Hermitian matrix
-// per workgroup, the matrix held in registers.
-//
-// The paper diagonalizes every traveling-cluster Hamiltonian exactly
-// (Sec. II(b); Fig. 2 steps (b), (d)) at a cost ~ (matrix dimension)^3.  Here a
-// workgroup of G x G threads reduces the matrix to real symmetric tridiagonal
-// form with complex Householder reflectors (unblocked, one column per step),
-// then finds every eigenvalue by Sturm-count bisection in FP64 and sums the
-// grand potential  F = sum_i [min(x_i,0) - T log1p(exp(-|x_i|/T))],
-// x_i = eps_i - mu,  in FP64.
+// Householder reduction of one dense complex Hermitian matrix per workgroup to
+// real symmetric tridiagonal form, storing only the lower triangle in
+// registers.  Used where the full matrix does not fit the register file
+// (FP64 matrices above dimension 128); the full-storage reducer is preferred
+// elsewhere because it needs no column partial sums.
 //
 // Data layout.  Element (i, j) of the n x n matrix lives in thread
 // (tr, tc) = (i mod G, j mod G), local block (li, lj) = (i / G, j / G); only the
 // lower triangle is stored (li >= lj, and inside a diagonal local block only
-// tr >= tc carries data, the rest stays zero).  A thread therefore holds
-// LR(LR+1)/2 complex numbers, LR = ceil(n/G), and the whole matrix never leaves
-// the register file.  Vectors of each step (current column, reflector, A*v)
-// are exchanged through LDS.
-//
-// One reduction step k (trailing block B = A[k+1:, k+1:], column x = A[k+1:, k]):
-//   reflector   beta = -sign(Re x_0) ||x||, tau = (beta - x_0)/beta,
-//               v = (1, x_1.. / (x_0 - beta)), so (I - tau v v^H)^H x = beta e_1
-//   y = B v                  (row partials + column partials, summed in LDS)
-//   w = tau y - (|tau|^2/2) Re(v^H y) v
-//   B <- B - v w^H - w v^H   (the two-sided update H^H B H)
-// and beta becomes the off-diagonal e_k (only e_k^2 enters the eigenvalues).
+// tr >= tc carries data, the rest stays zero).  y = A v is assembled from row
+// partials (lower part) and column partials (upper part, via conj(A_ji)) that
+// are summed through LDS.  The step algebra is that of reduce_full.hpp.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <stdint.h>
 
-namespace tca {
+#include "cplx.hpp"
 
-template <typename R>
-struct cx {
-  R re, im;
-};
+namespace tca {
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -44,7 +27,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 template <int G, int LR, typename R>
-struct Solver {
+struct ReduceLower {
   static constexpr int NT = G * G;            // threads per workgroup
   static constexpr int NW = NT / 64;          // wavefronts per workgroup
   static constexpr int NP = G * LR;           // padded dimension
@@ -52,24 +35,39 @@ struct Solver {
   static constexpr int PITCH = NP + 1;        // LDS row pitch of partial sums
   static_assert(NT % 64 == 0, "workgroup must be whole wavefronts");
 
+  static constexpr int MINW = 1;  // minimum wavefronts per SIMD (launch bounds)
+
   struct Smem {
+    double d[NP];
+    double e2[NP];
     cx<R> x[2][NP];      // current column (double-buffered)
     cx<R> y[NP];         // B v
     cx<R> pr[G * PITCH]; // row partials   [tc][i]
     cx<R> pc[G * PITCH]; // column partials [tr][j]
-    double d[NP];        // tridiagonal diagonal
-    double e2[NP];       // squared off-diagonal
-    double ea[NP];       // |off-diagonal|
-    double ev[NP];       // eigenvalues, ascending
-    double red[NW];
   };
 
   static __device__ __forceinline__ constexpr int idx(int li, int lj) { return li * (li + 1) / 2 + lj; }
 
+  // Fill the registers from lower(i, j) (i >= j).
+  template <class F>
+  static __device__ __forceinline__ void load(cx<R> (&A)[NLOC], const int n, F&& lower) {
+    const int tr = threadIdx.x / G, tc = threadIdx.x % G;
+#pragma unroll
+    for (int li = 0; li < LR; ++li) {
+#pragma unroll
+      for (int lj = 0; lj <= li; ++lj) {
+        const int i = tr + G * li, j = tc + G * lj;
+        cx<R> v = {R(0), R(0)};
+        if (i < n && (li > lj || tr >= tc)) v = lower(i, j);
+        A[idx(li, lj)] = v;
+      }
+    }
+  }
+
   // Copy column k (rows k+1..n-1) of the register matrix to LDS; also write
   // the diagonal entry d[k] and, at the last column, the final 2x2 entries.
   static __device__ __forceinline__ void write_col(int n, int k, const cx<R> (&A)[NLOC],
-                                                   cx<R>* xb, Smem& sm) {
+                                                   cx<R>* xb, double* d, double* e2) {
     const int tid = threadIdx.x, tr = tid / G, tc = tid % G;
     const int kb = k / G, kc = k % G;
 #pragma unroll
@@ -80,28 +78,29 @@ struct Solver {
           const int i = tr + G * li;
           const cx<R> a = A[idx(li, lj)];
           if (i > k && i < n) xb[i] = a;
-          if (i == k) sm.d[k] = (double)a.re;
+          if (i == k) d[k] = (double)a.re;
           if (k == n - 2 && i == n - 1) {
             const double ar = (double)a.re, ai = (double)a.im;
-            sm.e2[k] = ar * ar + ai * ai;
-            sm.ea[k] = sqrt(ar * ar + ai * ai);
+            e2[k] = ar * ar + ai * ai;
           }
         }
         if (k == n - 2 && lj == (n - 1) / G && li == lj && tr == (n - 1) % G && tc == (n - 1) % G)
-          sm.d[n - 1] = (double)A[idx(li, lj)].re;
+          d[n - 1] = (double)A[idx(li, lj)].re;
       }
     }
   }
 
   // Householder reduction to (d, e2); leaves them in LDS.
-  static __device__ void tridiagonalize(const int n, cx<R> (&A)[NLOC], Smem& sm) {
+  static __device__ void run(const int n, cx<R> (&A)[NLOC], Smem& sm, double* __restrict__ dg,
+                             double* __restrict__ e2g) {
+    double* d = sm.d;
+    double* e2 = sm.e2;
     const int tid = threadIdx.x, tr = tid / G, tc = tid % G, lane = tid & 63;
     if (n == 1) {
-      if (tid == 0) sm.d[0] = (double)A[0].re;
-      __syncthreads();
+      if (tid == 0) dg[0] = (double)A[0].re;
       return;
     }
-    write_col(n, 0, A, sm.x[0], sm);
+    write_col(n, 0, A, sm.x[0], d, e2);
     __syncthreads();
     int buf = 0;
     for (int k = 0; k < n - 2; ++k) {
@@ -128,8 +127,7 @@ struct Solver {
         sci = -di / den;
       }
       if (tid == 0) {
-        sm.e2[k] = (double)beta * (double)beta;
-        sm.ea[k] = fabs((double)beta);
+        e2[k] = (double)beta * (double)beta;
       }
       auto vget = [&](int i) -> cx<R> {
         if (i == k + 1) return {R(1), R(0)};
@@ -232,75 +230,16 @@ struct Solver {
           a.im -= ms * ui;
         }
       }
-      write_col(n, k + 1, A, sm.x[buf ^ 1], sm);
+      write_col(n, k + 1, A, sm.x[buf ^ 1], d, e2);
       buf ^= 1;
       __syncthreads();
     }
+    for (int i = threadIdx.x; i < n; i += NT) {
+      dg[i] = d[i];
+      if (i < n - 1) e2g[i] = e2[i];
+    }
   }
 
-  // Number of eigenvalues of the tridiagonal (d, e2) below x (Sturm count of
-  // the LDL^T pivots, with tiny pivots replaced by -pivmin).
-  static __device__ __forceinline__ int sturm(const int n, const double x, const double* d,
-                                              const double* e2, const double pivmin) {
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int c = q < 0.0;
-    for (int i = 1; i < n; ++i) {
-      q = (d[i] - x) - e2[i - 1] / q;
-      if (fabs(q) < pivmin) q = -pivmin;
-      c += q < 0.0;
-    }
-    return c;
-  }
-
-  // All eigenvalues by bisection (FP64), ascending, into sm.ev.
-  static __device__ void eigenvalues(const int n, Smem& sm) {
-    const int tid = threadIdx.x;
-    double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? sm.ea[i - 1] : 0.0) + (i < n - 1 ? sm.ea[i] : 0.0);
-      lo = fmin(lo, sm.d[i] - r);
-      hi = fmax(hi, sm.d[i] + r);
-      if (i < n - 1) emax2 = fmax(emax2, sm.e2[i]);
-    }
-    const double pivmin = DBL_MIN * fmax(1.0, emax2);
-    const double span = fmax(fabs(lo), fabs(hi));
-    const double widen = 2.0 * DBL_EPSILON * span * (double)n + pivmin;
-    lo -= widen;
-    hi += widen;
-    const double tol = 2.0 * DBL_EPSILON * span + pivmin;
-    for (int j = tid; j < n; j += NT) {
-      double a = lo, b = hi;
-      while (b - a > tol) {
-        const double mid = 0.5 * (a + b);
-        if (mid <= a || mid >= b) break;
-        if (sturm(n, mid, sm.d, sm.e2, pivmin) > j)
-          b = mid;
-        else
-          a = mid;
-      }
-      sm.ev[j] = 0.5 * (a + b);
-    }
-    __syncthreads();
-  }
-
-  // F = sum_i [min(x,0) - T log1p(exp(-|x|/T))], x = ev_i - mu (FP64), result
-  // valid in thread 0; fixed reduction order.
-  static __device__ double free_energy(const int n, const double T, const double mu, Smem& sm) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double acc = 0.0;
-    for (int j = tid; j < n; j += NT) {
-      const double x = sm.ev[j] - mu;
-      acc += fmin(x, 0.0) - T * log1p(exp(-fabs(x) / T));
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) sm.red[wave] = acc;
-    __syncthreads();
-    double F = 0.0;
-    if (tid == 0)
-      for (int w = 0; w < NW; ++w) F += sm.red[w];
-    return F;
-  }
 };
 
 }  // namespace tca

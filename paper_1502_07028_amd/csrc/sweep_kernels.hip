@@ -1,0 +1,238 @@
+// Kernels of a sweep around the cluster solves:
+//  decide_kernel     Metropolis decisions of one parallel block in an order
+//                    equivalent to the sequential sweep (Sec. II(c) steps
+//                    (e)-(f)), committing accepted spins;
+//  classify_kernel   per-update cluster size classes of one block;
+//  init / S(q)       initial spins and the structure factor of Eq. (2).
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace tca {
+
+// -------------------------------------------------------------------------
+// Change of the classical superexchange energy, evaluated one rounded
+// operation at a time: neighbour sum (-x, +x, -y, +y), difference, dot.
+__device__ __attribute__((noinline)) double classical_delta(const double* S, int L,
+                                                            int px, int py, const double* sn,
+                                                            double JAF) {
+#pragma clang fp contract(off)
+  const int xm = (px + L - 1) % L, xp = (px + 1) % L, ym = (py + L - 1) % L, yp = (py + 1) % L;
+  const double* a = S + 3 * (xm + L * py);
+  const double* b = S + 3 * (xp + L * py);
+  const double* c = S + 3 * (px + L * ym);
+  const double* d = S + 3 * (px + L * yp);
+  const double* s = S + 3 * (px + L * py);
+  double acc[3], df[3];
+  for (int k = 0; k < 3; ++k) {
+    acc[k] = ((a[k] + b[k]) + c[k]) + d[k];
+    df[k] = sn[k] - s[k];
+  }
+  double dot = df[0] * acc[0];
+  dot = dot + df[1] * acc[1];
+  dot = dot + df[2] * acc[2];
+  return JAF * dot;
+}
+
+// Metropolis decisions of block K.  Each cluster's dF came from the
+// block-start state, which equals the state the sequential sweep would have
+// shown it (no cluster of a block contains a site visited earlier in that
+// block).  The classical term reads the -x and -y lattice neighbours, which
+// may belong to the same block and be decided earlier in raster order, so with
+// J_AF != 0 the sites are processed by anti-diagonals i + j = const of the
+// block: every site is decided after both of those neighbours, exactly as in
+// the sequential order.  With J_AF == 0 all decisions are independent.
+__global__ __launch_bounds__(1024) void decide_kernel(double* S,
+                                                      const double* __restrict__ Fpair,
+                                                      BlockGeom g, ModelParams m, uint64_t sweep,
+                                                      double T, int Lc_fixed, int4 classes,
+                                                      int n_classes, int K,
+                                                      tca_update_record* __restrict__ logbuf,
+                                                      unsigned long long* __restrict__ counters) {
+  const int h = g.h, L = g.L;
+  const bool wave = (m.JAF != 0.0);
+  const int ndiag = wave ? 2 * h - 1 : 1;
+  unsigned long long nacc = 0, nnear = 0;
+  for (int dd = 0; dd < ndiag; ++dd) {
+    const int lo = wave ? max(0, dd - (h - 1)) : 0;
+    const int cnt = wave ? (min(dd, h - 1) - lo + 1) : h * h;
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+      int i, j;
+      if (wave) {
+        i = lo + q;
+        j = dd - i;
+      } else {
+        i = q % h;
+        j = q / h;
+      }
+      const int c = i + h * j;
+      const int px = g.x0 + i, py = g.y0 + j, site = px + L * py;
+      double sn[3];
+      sphere_point(m.seed, sweep, site, kStreamProposal, sn);
+      const double dF = Fpair[2 * c + 1] - Fpair[2 * c];
+      const double dE = dF + classical_delta(S, L, px, py, sn, m.JAF);
+      const U64x4 r = philox4x64_10(m.seed, 0, sweep, site, kStreamMetropolis, 0);
+      const double u = u53(r.w0);
+      const bool acc = (dE <= 0.0) || (u < exp(-dE / T));
+      bool near = false;
+      if (u > 0.0) near = fabs(dE + T * log(u)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+      if (acc) {
+        S[3 * site + 0] = sn[0];
+        S[3 * site + 1] = sn[1];
+        S[3 * site + 2] = sn[2];
+      }
+      nacc += acc;
+      nnear += near;
+      if (logbuf != nullptr) {
+        int Lc = Lc_fixed;
+        if (n_classes > 0) {
+          const int k = size_class(m.seed, sweep, site, n_classes);
+          Lc = k == 0 ? classes.x : k == 1 ? classes.y : k == 2 ? classes.z : classes.w;
+        }
+        tca_update_record rec;
+        rec.site = site;
+        rec.Lc = (int16_t)Lc;
+        rec.accept = acc ? 1 : 0;
+        rec.flags = near ? 1 : 0;
+        rec.dF = dF;
+        rec.dE = dE;
+        rec.u = u;
+        logbuf[(size_t)K * h * h + c] = rec;
+      }
+    }
+    if (wave) __syncthreads();
+  }
+  if (nacc) atomicAdd(&counters[0], nacc);
+  if (nnear) atomicAdd(&counters[1], nnear);
+  if (threadIdx.x == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
+}
+
+__global__ void classify_kernel(int4 classes, int n_classes, BlockGeom g, uint64_t seed,
+                                uint64_t sweep, int32_t* __restrict__ count,
+                                int32_t* __restrict__ list) {
+  const int hh = g.h * g.h;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= hh) return;
+  const int site = (g.x0 + c % g.h) + g.L * (g.y0 + c / g.h);
+  const int k = size_class(seed, sweep, site, n_classes);
+  const int pos = atomicAdd(&count[k], 1);
+  list[k * hh + pos] = c;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void init_spins_kernel(double* S, int L, int kind, uint64_t seed) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= L * L) return;
+  double s[3] = {0.0, 0.0, 1.0};
+  if (kind == TCA_INIT_RANDOM) {
+    sphere_point(seed, kInitSweep, (uint64_t)p, kStreamInit, s);
+  } else if (kind == TCA_INIT_NEEL) {
+    const int x = p % L, y = p / L;
+    s[2] = ((x + y) & 1) ? -1.0 : 1.0;
+  }
+  S[3 * p + 0] = s[0];
+  S[3 * p + 1] = s[1];
+  S[3 * p + 2] = s[2];
+}
+
+// S(q) by a separable DFT: rows first (x -> qx), then columns (y -> qy).
+__global__ void sq_rows_kernel(const double* __restrict__ S, int L, double* __restrict__ W) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;  // o = qx + L*y
+  if (o >= L * L) return;
+  const int qx = o % L, y = o / L;
+  double re[3] = {0, 0, 0}, im[3] = {0, 0, 0};
+  for (int x = 0; x < L; ++x) {
+    const int ph = (int)(((long long)qx * x) % L);
+    double sn, cs;
+    sincospi(2.0 * ph / L, &sn, &cs);
+    const double* s = S + 3 * (x + L * y);
+    for (int a = 0; a < 3; ++a) {
+      re[a] += s[a] * cs;
+      im[a] -= s[a] * sn;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    W[6 * o + 2 * a] = re[a];
+    W[6 * o + 2 * a + 1] = im[a];
+  }
+}
+
+__global__ void sq_cols_kernel(const double* __restrict__ W, int L, double* __restrict__ Sq) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;  // o = qx + L*qy
+  if (o >= L * L) return;
+  const int qx = o % L, qy = o / L;
+  double tot = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double re = 0.0, im = 0.0;
+    for (int y = 0; y < L; ++y) {
+      const int ph = (int)(((long long)qy * y) % L);
+      double sn, cs;
+      sincospi(2.0 * ph / L, &sn, &cs);
+      const double wr = W[6 * (qx + L * y) + 2 * a], wi = W[6 * (qx + L * y) + 2 * a + 1];
+      re += wr * cs + wi * sn;
+      im += wi * cs - wr * sn;
+    }
+    tot += re * re + im * im;
+  }
+  const double N = (double)L * L;
+  Sq[o] = tot / (N * N);
+}
+
+static int4 pack_classes(const int32_t* c, int n) {
+  int4 r = make_int4(0, 0, 0, 0);
+  if (n > 0) r.x = c[0];
+  if (n > 1) r.y = c[1];
+  if (n > 2) r.z = c[2];
+  if (n > 3) r.w = c[3];
+  return r;
+}
+
+hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g, uint64_t seed,
+                           uint64_t sweep, ClassLists cl, hipStream_t st) {
+  const int hh = g.h * g.h;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cl.count, 4);
+  hipLaunchKernelGGL(classify_kernel, dim3((hh + 255) / 256), dim3(256), 0, st,
+                     pack_classes(classes_Lc, n_classes), n_classes, g, seed, sweep, cl.count,
+                     cl.list);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m,
+                         uint64_t sweep, double T, int Lc_fixed, const int32_t* classes_Lc,
+                         int n_classes, int K, tca_update_record* log_dev,
+                         unsigned long long* counters, hipStream_t st) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, Fpair, g, m, sweep, T,
+                     Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, K, log_dev,
+                     counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_spins(double* S, int L, int kind, uint64_t seed, hipStream_t st) {
+  const int N = L * L;
+  hipLaunchKernelGGL(init_spins_kernel, dim3((N + 255) / 256), dim3(256), 0, st, S, L, kind, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_sq(const double* S, int L, double* work, double* Sq, hipStream_t st) {
+  const int N = L * L;
+  hipLaunchKernelGGL(sq_rows_kernel, dim3((N + 255) / 256), dim3(256), 0, st, S, L, work);
+  hipLaunchKernelGGL(sq_cols_kernel, dim3((N + 255) / 256), dim3(256), 0, st, work, L, Sq);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace tca

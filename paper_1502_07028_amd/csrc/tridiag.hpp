@@ -1,0 +1,202 @@
+// Eigenvalues of a real symmetric tridiagonal matrix T (diagonal d, squared
+// off-diagonal e2) and the fermionic grand potential of its spectrum, FP64.
+//
+// Sturm sequence.  The leading principal minors of T - x,
+//   P_0 = 1,  P_1 = d_0 - x,  P_{i+1} = (d_i - x) P_i - e2_{i-1} P_{i-1},
+// change sign exactly as often as T has eigenvalues below x (their ratios
+// P_{i+1}/P_i are the pivots of the LDL^T factorization of T - x).  Each step
+// costs one FMA on the critical path (the division of the pivot form is
+// avoided); every eight steps the pair (P_i, P_{i-1}) is rescaled by an exact
+// power of two so that it stays far from overflow and underflow, which changes
+// no sign.  An exactly zero minor takes the sign of its zero bit, which yields
+// the same total count as replacing a zero pivot by a tiny negative one.
+//
+// Search.  Eigenvalue j (ascending) is bracketed by bisection only until
+// [a, b] holds eigenvalue j alone (and two more halvings); then Newton steps
+// on det(T - x) = P_n(x) finish it, the derivative P_n' coming from the
+// differentiated recurrence P'_{i+1} = -P_i + (d_i - x) P'_i - e2_{i-1} P'_{i-1}.
+// Every evaluation also gives the Sturm count that keeps the bracket; a Newton
+// iterate leaving the bracket is replaced by the midpoint.  Newton stops when
+// its step is below the tolerance, or is small and fails to halve or leaves
+// the bracket (the rounding noise of det(T - x) is reached); an eigenvalue
+// that cannot be isolated (a cluster narrower than the tolerance) is finished
+// by plain bisection.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <float.h>
+
+namespace tca {
+
+struct TriBounds {
+  double lo, hi, tol;
+};
+
+// Gershgorin bounds widened by a few ulps.
+__device__ inline TriBounds tri_bounds(const int n, const double* d, const double* e2) {
+  double lo = DBL_MAX, hi = -DBL_MAX;
+  double ep = 0.0;  // |e_{i-1}|
+  for (int i = 0; i < n; ++i) {
+    const double en = (i < n - 1) ? sqrt(e2[i]) : 0.0;
+    lo = fmin(lo, d[i] - ep - en);
+    hi = fmax(hi, d[i] + ep + en);
+    ep = en;
+  }
+  TriBounds b;
+  const double span = fmax(fmax(fabs(lo), fabs(hi)), DBL_MIN);
+  const double widen = 2.0 * DBL_EPSILON * span * (double)n;
+  b.lo = lo - widen;
+  b.hi = hi + widen;
+  b.tol = 2.0 * DBL_EPSILON * span;
+  return b;
+}
+
+__device__ __forceinline__ unsigned sign_change(double a, double b) {
+  return (unsigned)(__double2hiint(a) ^ __double2hiint(b)) >> 31;
+}
+
+// power-of-two factor bringing a magnitude m >= 0 back into [2^-200, 2^200]
+__device__ __forceinline__ double rescale_factor(double m) {
+  return m > 0x1p200 ? 0x1p-200 : (m < 0x1p-200 && m > 0.0 ? 0x1p200 : 1.0);
+}
+
+constexpr int kSturmGroup = 8;  // steps between rescalings (one scalar-load wait each)
+
+// Number of eigenvalues below x.
+__device__ __forceinline__ int sturm_count(const int n, const double x, const double* d,
+                                           const double* e2) {
+  double pm = 1.0, p = d[0] - x;
+  unsigned c = sign_change(p, pm);
+  int i = 1;
+  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
+    double dd[kSturmGroup], ee[kSturmGroup];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+      const double pn = fma(dd[u] - x, p, -ee[u] * pm);
+      c += sign_change(pn, p);
+      pm = p;
+      p = pn;
+    }
+    const double f = rescale_factor(fmax(fabs(p), fabs(pm)));
+    p *= f;
+    pm *= f;
+  }
+  for (; i < n; ++i) {
+    const double pn = fma(d[i] - x, p, -e2[i - 1] * pm);
+    c += sign_change(pn, p);
+    pm = p;
+    p = pn;
+  }
+  return (int)c;
+}
+
+// Sturm count at x and the Newton step P_n/P_n' for det(T - x).
+__device__ __forceinline__ int sturm_newton(const int n, const double x, const double* d,
+                                            const double* e2, double* step) {
+  double pm = 1.0, p = d[0] - x;
+  double qm = 0.0, q = -1.0;  // derivatives
+  unsigned c = sign_change(p, pm);
+  int i = 1;
+  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
+    double dd[kSturmGroup], ee[kSturmGroup];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+      const double dx = dd[u] - x, e = ee[u];
+      const double pn = fma(dx, p, -e * pm);
+      const double qn = fma(dx, q, -fma(e, qm, p));
+      c += sign_change(pn, p);
+      pm = p;
+      p = pn;
+      qm = q;
+      q = qn;
+    }
+    const double f = rescale_factor(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))));
+    p *= f;
+    pm *= f;
+    q *= f;
+    qm *= f;
+  }
+  for (; i < n; ++i) {
+    const double dx = d[i] - x, e = e2[i - 1];
+    const double pn = fma(dx, p, -e * pm);
+    const double qn = fma(dx, q, -fma(e, qm, p));
+    c += sign_change(pn, p);
+    pm = p;
+    p = pn;
+    qm = q;
+    q = qn;
+  }
+  *step = p / q;
+  return (int)c;
+}
+
+// Eigenvalue j of T.
+__device__ inline double tri_eigenvalue(const int n, const int j, const double* d, const double* e2,
+                                        const TriBounds& B) {
+  double a = B.lo, b = B.hi;
+  int ca = 0, cb = n;
+  int extra = 2;
+  while (b - a > B.tol) {
+    if (ca == j && cb == j + 1 && extra-- <= 0) break;
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    const int c = sturm_count(n, mid, d, e2);
+    if (c > j) {
+      b = mid;
+      cb = c;
+    } else {
+      a = mid;
+      ca = c;
+    }
+  }
+  if (b - a <= B.tol) return 0.5 * (a + b);
+  double x = 0.5 * (a + b);
+  double last = b - a;
+  for (int it = 0; it < 12; ++it) {
+    double step;
+    const int c = sturm_newton(n, x, d, e2, &step);
+    if (c > j)
+      b = x;
+    else
+      a = x;
+    if (b - a <= B.tol) return 0.5 * (a + b);
+    double xn = x - step;
+    const bool inside = xn > a && xn < b;
+    const double st = fabs(step);
+    if (st <= B.tol) return xn;
+    // a small step that no longer halves, or that points out of the bracket,
+    // is rounding noise of det(T - x): x is as accurate as a bisection to the
+    // tolerance (in the quadratic regime a step of 1e5 tol is followed by one
+    // far below half of it)
+    if (st <= 1e5 * B.tol && (st > 0.5 * last || !inside)) return x;
+    if (!inside) xn = 0.5 * (a + b);
+    last = inside ? st : b - a;
+    x = xn;
+  }
+  while (b - a > B.tol) {
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    if (sturm_count(n, mid, d, e2) > j)
+      b = mid;
+    else
+      a = mid;
+  }
+  return 0.5 * (a + b);
+}
+
+// Grand potential term of one level: min(x,0) - T log1p(exp(-|x|/T)), x = eps - mu.
+__device__ __forceinline__ double omega_term(const double eps, const double T, const double mu) {
+  const double x = eps - mu;
+  return fmin(x, 0.0) - T * log1p(exp(-fabs(x) / T));
+}
+
+}  // namespace tca
