@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define TCA_ABI_VERSION 1
+#define TCA_ABI_VERSION 2
 
 typedef enum {
   TCA_OK = 0,
@@ -75,10 +75,14 @@ typedef struct {
   int32_t site;   /* lattice site p */
   int16_t Lc;     /* cluster linear size used */
   uint8_t accept; /* 1 if the proposal was accepted */
-  uint8_t flags;  /* bit 0: near-threshold (|dE + T ln u| <= 1e-9 max(|dE|,1e-3)) */
-  double dF;      /* F_new - F_old of the cluster */
-  double dE;      /* dF + classical change */
+  uint8_t flags;  /* bit 0: near-threshold of the exact test (|T ln u - rhs| <= 1e-9 max(|dE|,1e-3));
+                     bit 1: the update reached the exact stage (always set without a surrogate);
+                     bit 2: near-threshold of the surrogate stage */
+  double dF;      /* F_new - F_old of the cluster (NaN if the surrogate stage rejected it) */
+  double dE;      /* dF + classical change (NaN likewise) */
   double u;       /* the Metropolis uniform */
+  float dS_f;     /* surrogate dF of the move (0 without a surrogate) */
+  float dS_r;     /* surrogate dF of the reverse move */
 } tca_update_record;
 
 typedef struct {
@@ -96,9 +100,13 @@ typedef struct {
   int64_t reduce_launches;
   int64_t eig_launches;
   int64_t decide_launches;
+  int64_t stage1_passed;    /* updates that reached the exact stage (= updates without a surrogate) */
+  double surrogate_ms;      /* with TCA_FLAG_PROFILE: delayed-acceptance stage 1 (features, MLP, flags) */
+  int64_t surrogate_launches;
 } tca_sweep_stats;
 
 typedef struct tca_ctx tca_ctx;
+typedef struct tca_surrogate tca_surrogate;
 
 /* Create a lattice context on the current HIP device.
  *   p          host; validated (TCA_E_INVAL on a bad size, precision or flag)
@@ -160,6 +168,96 @@ int tca_heevals_batched(const double* A, int32_t n, int32_t batch, int32_t preci
  * hip_stream without synchronization; used for timing. */
 int tca_heevals_batched_dev(const double* A, int32_t n, int32_t batch, int32_t precision,
                             double T, double mu, double* w, double* F, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learned first stage of delayed-acceptance Metropolis.
+ *
+ * The paper has no learned component: this is the delayed-acceptance scheme
+ * of Christen & Fox (2005) put in front of the exact cluster energy of
+ * Sec. II(c) (Fig. 2 steps (b)-(e)), which stays the second stage, so the
+ * chain keeps the stationary law of the plain TCA sweep for any surrogate.
+ * The surrogate is an MLP n_in -> H -> H -> 1 with SiLU after the first two
+ * layers, n_in = 3 Lc^2 + 4: the cluster spins in cluster order (x, y, z),
+ * the proposed spin, and T/0.1; it predicts F_new - F_old of the cluster.
+ * Weights are FP32 (trained by the library's own FP32 kernels: forward,
+ * backward of the mean squared error, Adam with beta1 0.9, beta2 0.999,
+ * eps 1e-8); inference inside a sweep runs in BF16 on the matrix cores
+ * (inputs, W1, W2 and the two hidden activations rounded to bfloat16, FP32
+ * accumulation).
+ * Flat parameter layout (FP32): W1 [H][n_in] row-major, b1 [H], W2 [H][H],
+ * b2 [H], W3 [H], b3 [1].
+ * A surrogate's device memory belongs to the library until
+ * tca_surrogate_destroy(); all work is issued on its stream and finished
+ * before a call returns.  Errors as for the lattice entry points.
+ * ---------------------------------------------------------------------- */
+
+/* New surrogate for clusters of linear size Lc (2..10) and hidden width
+ * `hidden` (16..1024, multiple of 16); weights uniform in +-sqrt(6/(fan_in +
+ * fan_out)) from Philox(seed), biases 0; dataset capacity `capacity` rows
+ * (>= 0) in device memory. */
+int tca_surrogate_create(int32_t Lc, int32_t hidden, uint64_t seed, int64_t capacity,
+                         void* hip_stream, tca_surrogate** out);
+
+/* Release the surrogate (NULL accepted).  Detach it from every context that
+ * uses it first. */
+int tca_surrogate_destroy(tca_surrogate* s);
+
+/* Host out: number of parameters, input width, rows held in the dataset. */
+int tca_surrogate_info(tca_surrogate* s, int64_t* nparams, int32_t* n_in, int64_t* rows);
+
+/* Copy the FP32 parameters out to / in from host memory (nparams floats). */
+int tca_surrogate_save(tca_surrogate* s, float* params);
+int tca_surrogate_load(tca_surrogate* s, const float* params);
+
+/* Training data from the exact method: run nsweeps plain sweeps of context c
+ * (Sec. II(c) semantics, as tca_sweep without a surrogate) and append one row
+ * per update -- features of the proposed move in the block-start state and
+ * the exact F_new - F_old -- to the dataset.  c must use a fixed cluster size
+ * equal to the surrogate's Lc, and nsweeps * L*L rows must fit the remaining
+ * capacity (else TCA_E_INVAL).  T as for tca_sweep; st NULL or filled. */
+int tca_surrogate_collect(tca_surrogate* s, tca_ctx* c, const double* T, int32_t nsweeps,
+                          tca_sweep_stats* st);
+
+/* Copy dataset rows [r0, r0 + rows) out to host memory (X: rows x n_in,
+ * y: rows); TCA_E_INVAL if the range is not inside the dataset. */
+int tca_surrogate_get_rows(tca_surrogate* s, int64_t r0, int64_t rows, float* X, float* y);
+
+/* Append host rows (rows x n_in features, rows targets) to the dataset. */
+int tca_surrogate_add_rows(tca_surrogate* s, const float* X, const float* y, int64_t rows);
+
+/* `steps` Adam steps on minibatches of `batch` rows drawn (Philox, with
+ * replacement) from the first rows - n_hold rows of the dataset, where
+ * n_hold = floor(holdout * rows) rows at the end are held out (0 <= holdout
+ * < 1).  Host out (each may be NULL): mean training loss of the last
+ * min(steps, 50) steps, RMSE of the FP32 and of the BF16 network on the
+ * held-out rows (0 if none). */
+int tca_surrogate_train(tca_surrogate* s, int32_t steps, int32_t batch, float lr, double holdout,
+                        double* train_mse, double* holdout_rmse_fp32,
+                        double* holdout_rmse_bf16);
+
+/* Loss mean((f(X) - y)^2) and its gradient (nparams floats, parameter
+ * layout) for host rows; the weights are not changed. */
+int tca_surrogate_grad(tca_surrogate* s, const float* X, const float* y, int32_t rows,
+                       float* grad, double* loss);
+
+/* One Adam step with a host gradient (nparams floats). */
+int tca_surrogate_adam_step(tca_surrogate* s, const float* grad, float lr);
+
+/* Predictions for host rows (rows x n_in): bf16 = 0 the FP32 network,
+ * bf16 = 1 the BF16 inference path used inside sweeps. */
+int tca_surrogate_eval(tca_surrogate* s, const float* X, int32_t rows, int32_t bf16, float* out);
+
+/* Make s the first stage of delayed acceptance in every later tca_sweep on c
+ * (NULL: plain Metropolis again).  Needs a fixed cluster size equal to the
+ * surrogate's Lc (TCA_E_UNSUPPORTED with size classes).  Per update: stage 1
+ * passes iff u1 == 0 or ln u1 < min(0, -dS_f/T); only survivors are solved
+ * exactly, and a survivor is accepted iff u == 0 or
+ * ln u < -dE/T + min(0, -dS_r/T) - min(0, -dS_f/T), where dS_f and dS_r are
+ * the surrogate on the move and on its reverse (corner spin = proposal,
+ * proposing the old spin), u and u1 words 0 and 1 of the update's Metropolis
+ * Philox block.  The context keeps a pointer: the surrogate must outlive the
+ * attachment. */
+int tca_attach_surrogate(tca_ctx* c, tca_surrogate* s);
 
 /* Release the context and its device memory (NULL is accepted). */
 int tca_destroy(tca_ctx* c);

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtca.so")
 
-TCA_ABI_VERSION = 1
+TCA_ABI_VERSION = 2
 TCA_OK, TCA_E_INVAL, TCA_E_NOMEM, TCA_E_DEVICE, TCA_E_UNSUPPORTED = 0, -1, -2, -3, -4
 TCA_FP64, TCA_MIXED = 0, 1
 TCA_INIT_RANDOM, TCA_INIT_FERRO, TCA_INIT_NEEL, TCA_INIT_USER = 0, 1, 2, 3
@@ -37,7 +37,7 @@ class tca_params(ctypes.Structure):
 class tca_update_record(ctypes.Structure):
     _fields_ = [("site", ctypes.c_int32), ("Lc", ctypes.c_int16), ("accept", ctypes.c_uint8),
                 ("flags", ctypes.c_uint8), ("dF", ctypes.c_double), ("dE", ctypes.c_double),
-                ("u", ctypes.c_double)]
+                ("u", ctypes.c_double), ("dS_f", ctypes.c_float), ("dS_r", ctypes.c_float)]
 
 
 class tca_sweep_stats(ctypes.Structure):
@@ -45,16 +45,21 @@ class tca_sweep_stats(ctypes.Structure):
                 ("near_threshold", ctypes.c_int64), ("elapsed_ms", ctypes.c_double),
                 ("reduce_ms", ctypes.c_double), ("eig_ms", ctypes.c_double),
                 ("decide_ms", ctypes.c_double), ("reduce_launches", ctypes.c_int64),
-                ("eig_launches", ctypes.c_int64), ("decide_launches", ctypes.c_int64)]
+                ("eig_launches", ctypes.c_int64), ("decide_launches", ctypes.c_int64),
+                ("stage1_passed", ctypes.c_int64), ("surrogate_ms", ctypes.c_double),
+                ("surrogate_launches", ctypes.c_int64)]
 
 
 RECORD_DTYPE = np.dtype([("site", "<i4"), ("Lc", "<i2"), ("accept", "u1"), ("flags", "u1"),
-                         ("dF", "<f8"), ("dE", "<f8"), ("u", "<f8")])
+                         ("dF", "<f8"), ("dE", "<f8"), ("u", "<f8"), ("dS_f", "<f4"),
+                         ("dS_r", "<f4")])
 assert RECORD_DTYPE.itemsize == ctypes.sizeof(tca_update_record)
 
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int32)
+_F = ctypes.POINTER(ctypes.c_float)
+_L = ctypes.POINTER(ctypes.c_int64)
 _SIGS = {
     "tca_init_lattice": [ctypes.POINTER(tca_params), _D, _P, ctypes.POINTER(_P)],
     "tca_sweep": [_P, _D, ctypes.c_int32, _P, ctypes.POINTER(tca_sweep_stats)],
@@ -68,6 +73,21 @@ _SIGS = {
                                 ctypes.c_double, ctypes.c_double, _P, _P, _P],
     "tca_destroy": [_P],
     "tca_abi_sizes": [_I],
+    "tca_surrogate_create": [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, _P,
+                             ctypes.POINTER(_P)],
+    "tca_surrogate_destroy": [_P],
+    "tca_surrogate_info": [_P, _L, _I, _L],
+    "tca_surrogate_save": [_P, _F],
+    "tca_surrogate_load": [_P, _F],
+    "tca_surrogate_collect": [_P, _P, _D, ctypes.c_int32, ctypes.POINTER(tca_sweep_stats)],
+    "tca_surrogate_add_rows": [_P, _F, _F, ctypes.c_int64],
+    "tca_surrogate_get_rows": [_P, ctypes.c_int64, ctypes.c_int64, _F, _F],
+    "tca_surrogate_train": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_double,
+                            _D, _D, _D],
+    "tca_surrogate_grad": [_P, _F, _F, ctypes.c_int32, _F, _D],
+    "tca_surrogate_adam_step": [_P, _F, ctypes.c_float],
+    "tca_surrogate_eval": [_P, _F, ctypes.c_int32, ctypes.c_int32, _F],
+    "tca_attach_surrogate": [_P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -93,6 +113,21 @@ def _check(status, where):
 
 def _dptr(a):
     return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _fptr(a):
+    return a.ctypes.data_as(_F) if a is not None else None
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _stats(st):
+    return {k: getattr(st, k) for k, _ in tca_sweep_stats._fields_}
 
 
 def _f64(a, shape=None):
@@ -150,11 +185,7 @@ def tca_sweep(ctx, T, nsweeps=None, log=False, N=None):
     st = tca_sweep_stats()
     _check(_lib.tca_sweep(ctx, _dptr(T), ns, recs.ctypes.data if recs is not None else None,
                           ctypes.byref(st)), "tca_sweep")
-    return recs, dict(updates=st.updates, accepted=st.accepted,
-                      near_threshold=st.near_threshold, elapsed_ms=st.elapsed_ms,
-                      reduce_ms=st.reduce_ms, eig_ms=st.eig_ms, decide_ms=st.decide_ms,
-                      reduce_launches=st.reduce_launches, eig_launches=st.eig_launches,
-                      decide_launches=st.decide_launches)
+    return recs, _stats(st)
 
 
 def tca_cluster_eigvals(ctx, sites, Lc=None, proposed=None, ld=None):
@@ -224,6 +255,11 @@ class Lattice:
     def sweep(self, T, log=False):
         return tca_sweep(self.ctx, T, log=log, N=self.N)
 
+    def attach(self, surrogate):
+        """Use a Surrogate as the first stage of delayed acceptance (None: plain)."""
+        tca_attach_surrogate(self.ctx, surrogate.handle if surrogate is not None else None)
+        self._sg = surrogate
+
     def eigvals(self, sites, Lc=None, proposed=None):
         return tca_cluster_eigvals(self.ctx, sites, Lc, proposed)
 
@@ -244,6 +280,160 @@ class Lattice:
         if self.ctx:
             tca_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- surrogate
+def tca_surrogate_create(Lc, hidden=256, seed=1, capacity=0, stream=None):
+    h = _P()
+    _check(_lib.tca_surrogate_create(int(Lc), int(hidden), int(seed), int(capacity), stream,
+                                     ctypes.byref(h)), "tca_surrogate_create")
+    return h.value
+
+
+def tca_surrogate_destroy(sg):
+    _check(_lib.tca_surrogate_destroy(sg), "tca_surrogate_destroy")
+
+
+def tca_surrogate_info(sg):
+    n, k, r = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.tca_surrogate_info(sg, ctypes.byref(n), ctypes.byref(k), ctypes.byref(r)),
+           "tca_surrogate_info")
+    return n.value, k.value, r.value
+
+
+def tca_surrogate_save(sg):
+    n = tca_surrogate_info(sg)[0]
+    out = np.zeros(n, dtype=np.float32)
+    _check(_lib.tca_surrogate_save(sg, _fptr(out)), "tca_surrogate_save")
+    return out
+
+
+def tca_surrogate_load(sg, params):
+    v = _f32(params).ravel()
+    if v.size != tca_surrogate_info(sg)[0]:
+        raise ValueError("parameter vector has the wrong length")
+    _check(_lib.tca_surrogate_load(sg, _fptr(v)), "tca_surrogate_load")
+
+
+def tca_surrogate_collect(sg, ctx, T):
+    T = _f64(np.atleast_1d(T))
+    st = tca_sweep_stats()
+    _check(_lib.tca_surrogate_collect(sg, ctx, _dptr(T), len(T), ctypes.byref(st)),
+           "tca_surrogate_collect")
+    return _stats(st)
+
+
+def tca_surrogate_add_rows(sg, X, y):
+    n_in = tca_surrogate_info(sg)[1]
+    X = _f32(X, (-1, n_in))
+    y = _f32(y).ravel()
+    if len(y) != len(X):
+        raise ValueError("X and y row counts differ")
+    _check(_lib.tca_surrogate_add_rows(sg, _fptr(X), _fptr(y), len(y)), "tca_surrogate_add_rows")
+
+
+def tca_surrogate_get_rows(sg, r0, rows):
+    n_in = tca_surrogate_info(sg)[1]
+    X = np.zeros((int(rows), n_in), dtype=np.float32)
+    y = np.zeros(int(rows), dtype=np.float32)
+    _check(_lib.tca_surrogate_get_rows(sg, int(r0), int(rows), _fptr(X), _fptr(y)),
+           "tca_surrogate_get_rows")
+    return X, y
+
+
+def tca_surrogate_train(sg, steps, batch=1024, lr=1e-3, holdout=0.1):
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.tca_surrogate_train(sg, int(steps), int(batch), float(lr), float(holdout),
+                                    ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "tca_surrogate_train")
+    return dict(train_mse=a.value, holdout_rmse_fp32=b.value, holdout_rmse_bf16=c.value)
+
+
+def tca_surrogate_grad(sg, X, y):
+    n, n_in, _ = tca_surrogate_info(sg)
+    X = _f32(X, (-1, n_in))
+    y = _f32(y).ravel()
+    g = np.zeros(n, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(_lib.tca_surrogate_grad(sg, _fptr(X), _fptr(y), len(y), _fptr(g), ctypes.byref(loss)),
+           "tca_surrogate_grad")
+    return loss.value, g
+
+
+def tca_surrogate_adam_step(sg, grad, lr):
+    g = _f32(grad).ravel()
+    _check(_lib.tca_surrogate_adam_step(sg, _fptr(g), float(lr)), "tca_surrogate_adam_step")
+
+
+def tca_surrogate_eval(sg, X, bf16=True):
+    n_in = tca_surrogate_info(sg)[1]
+    X = _f32(X, (-1, n_in))
+    out = np.zeros(len(X), dtype=np.float32)
+    _check(_lib.tca_surrogate_eval(sg, _fptr(X), len(X), int(bool(bf16)), _fptr(out)),
+           "tca_surrogate_eval")
+    return out
+
+
+def tca_attach_surrogate(ctx, sg):
+    _check(_lib.tca_attach_surrogate(ctx, sg), "tca_attach_surrogate")
+
+
+class Surrogate:
+    """Owning wrapper of one tca_surrogate (the learned first stage)."""
+
+    def __init__(self, Lc, hidden=256, seed=1, capacity=0, stream=None):
+        self.handle = tca_surrogate_create(Lc, hidden, seed, capacity, stream)
+        self.Lc, self.hidden = int(Lc), int(hidden)
+
+    @property
+    def n_params(self):
+        return tca_surrogate_info(self.handle)[0]
+
+    @property
+    def n_in(self):
+        return tca_surrogate_info(self.handle)[1]
+
+    @property
+    def rows(self):
+        return tca_surrogate_info(self.handle)[2]
+
+    def params(self):
+        return tca_surrogate_save(self.handle)
+
+    def load(self, params):
+        tca_surrogate_load(self.handle, params)
+
+    def collect(self, lattice, T):
+        return tca_surrogate_collect(self.handle, lattice.ctx, T)
+
+    def add_rows(self, X, y):
+        tca_surrogate_add_rows(self.handle, X, y)
+
+    def get_rows(self, r0, rows):
+        return tca_surrogate_get_rows(self.handle, r0, rows)
+
+    def train(self, steps, batch=1024, lr=1e-3, holdout=0.1):
+        return tca_surrogate_train(self.handle, steps, batch, lr, holdout)
+
+    def grad(self, X, y):
+        return tca_surrogate_grad(self.handle, X, y)
+
+    def adam_step(self, grad, lr):
+        tca_surrogate_adam_step(self.handle, grad, lr)
+
+    def eval(self, X, bf16=True):
+        return tca_surrogate_eval(self.handle, X, bf16)
+
+    def close(self):
+        if self.handle:
+            tca_surrogate_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtca.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["cluster_kernels.hip", "sweep_kernels.hip", "api.hip"]
+SOURCES = ["cluster_kernels.hip", "sweep_kernels.hip", "surrogate.hip", "api.hip",
+           "api_surrogate.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # packed FP32 VALU forms stay disabled: plain FP32 code only
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

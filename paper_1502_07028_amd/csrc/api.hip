@@ -16,32 +16,16 @@
 #include <mutex>
 #include <vector>
 
+#include "ctx.hpp"
 #include "internal.hpp"
 
 using namespace tca;
 
-namespace {
-
+namespace tca {
 thread_local char g_err[512] = "";
-
-void set_err(const char* fmt, const char* a = "", int line = 0) {
-  snprintf(g_err, sizeof(g_err), fmt, a, line);
 }
 
-#define TCA_CK(expr)                                                   \
-  do {                                                                 \
-    hipError_t e_ = (expr);                                            \
-    if (e_ != hipSuccess) {                                            \
-      set_err("HIP error %s at api.hip:%d", hipGetErrorString(e_), __LINE__); \
-      return TCA_E_DEVICE;                                             \
-    }                                                                  \
-  } while (0)
-
-#define TCA_INVAL(msg)        \
-  do {                        \
-    set_err("%s", msg);       \
-    return TCA_E_INVAL;       \
-  } while (0)
+namespace {
 
 bool is_fin(double v) { return isfinite(v) != 0; }
 
@@ -54,43 +38,14 @@ bool unit_spins(const double* s, long n) {
   return true;
 }
 
-template <typename T>
-struct DevBuf {
-  T* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t n) { return hipMalloc((void**)&p, n * sizeof(T) + 16); }
-};
-
 }  // namespace
-
-struct tca_ctx {
-  tca_params p;
-  hipStream_t stream = nullptr;
-  int N = 0, h = 0;
-  double* S = nullptr;           // N x 3
-  double* F = nullptr;           // 2 * h*h grand potentials (old, new per cluster)
-  double* D = nullptr;           // 2 * h*h * ld tridiagonal diagonals
-  double* E2 = nullptr;          // 2 * h*h * ld squared off-diagonals
-  int32_t* nmat = nullptr;       // 2 * h*h matrix dimensions
-  int ld = 0;                    // 2 * (largest Lc)^2
-  int32_t* cls_count = nullptr;  // 4
-  int32_t* cls_list = nullptr;   // 4 * h*h
-  unsigned long long* counters = nullptr;  // 4
-  double* sq_work = nullptr;     // 6 N
-  double* sq_out = nullptr;      // N
-  uint64_t sweep_counter = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::vector<hipEvent_t> prof;  // event pool for TCA_FLAG_PROFILE
-};
 
 // Event pairs bracketing launches when profiling: pairs [2i, 2i+1].
 struct ProfRec {
   tca_ctx* c;
   bool on;
   size_t used = 0;
-  std::vector<int> kind;  // 0 reduce, 1 eigenvalues, 2 decide
+  std::vector<int> kind;  // 0 reduce, 1 eigenvalues, 2 decide, 3 surrogate stage
   hipError_t begin() {
     if (!on) return hipSuccess;
     while (c->prof.size() < 2 * (used + 1)) {
@@ -246,35 +201,46 @@ int tca_get_sweep_counter(tca_ctx* c, uint64_t* sc) {
   return TCA_OK;
 }
 
-int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* log,
-              tca_sweep_stats* st) {
-  g_err[0] = 0;
-  if (!c || !T) TCA_INVAL("NULL argument");
-  if (nsweeps < 0) TCA_INVAL("nsweeps < 0");
-  for (int s = 0; s < nsweeps; ++s)
-    if (!is_fin(T[s]) || T[s] <= 0.0) TCA_INVAL("temperatures must be finite and > 0");
+}  // extern "C"
+
+// Issue nsweeps sweeps on the context's stream (no synchronization).  With a
+// surrogate attached, each block first runs the delayed-acceptance stage 1
+// (features of the forward and reverse moves, BF16 MLP, pass flags and the
+// compacted list of survivors) and only the survivors are solved exactly.
+// With `collect`, every update's (features, dF) row is appended to the
+// surrogate's dataset starting at row `row0` (plain sweeps only).
+static int issue_sweeps(tca_ctx* c, const double* T, int nsweeps, tca_update_record* dlog,
+                     ProfRec& pr, tca_surrogate* collect, int64_t row0) {
   const int L = c->p.L, h = c->h, hh = h * h;
-  DevBuf<tca_update_record> dlog;
-  if (log && nsweeps > 0) {
-    hipError_t e = dlog.alloc((size_t)nsweeps * c->N);
-    if (e != hipSuccess) {
-      set_err("log allocation failed: %s", hipGetErrorString(e));
-      return TCA_E_NOMEM;
-    }
-  }
   const ModelParams m = model_of(c);
-  ProfRec pr{c, (c->p.flags & TCA_FLAG_PROFILE) != 0};
-  TCA_CK(launch_zero_u64(c->counters, 4, c->stream));
-  TCA_CK(hipEventRecord(c->ev0, c->stream));
+  tca_surrogate* sg = collect ? nullptr : c->sg;
+  if (sg && sg->bf16_stale) {
+    TCA_CK(sg_to_bf16(sg->W.p, sg->dm, sg->W1b.p, sg->W2b.p, c->stream));
+    sg->bf16_stale = false;
+  }
   for (int s = 0; s < nsweeps; ++s) {
     const uint64_t sweep = c->sweep_counter + (uint64_t)s;
     for (int K = 0; K < 4; ++K) {
       const BlockGeom g{L, h, h * (K & 1), h * (K >> 1)};
       const ReduceOut ro{c->D, c->E2, c->ld, c->nmat};
+      const int32_t* list = nullptr;
+      const int32_t* count = nullptr;
+      if (sg) {
+        TCA_CK(pr.begin());
+        TCA_CK(sg_block_features(c->S, g, c->p.Lc, m, sweep, T[s], sg->dm, c->da.Fin.p,
+                                 c->stream));
+        TCA_CK(sg_infer_bf16(c->da.Fin.p, 2 * hh, sg->W.p, sg->W1b.p, sg->W2b.p, sg->dm,
+                             SgInferBufs{c->da.H1.p, c->da.H2.p}, c->da.dS.p, c->stream));
+        TCA_CK(sg_stage1(c->da.dS.p, g, m, sweep, T[s], c->da.pass.p, c->da.count.p,
+                         c->da.list.p, c->stream));
+        TCA_CK(pr.end(3));
+        list = c->da.list.p;
+        count = c->da.count.p;
+      }
       TCA_CK(pr.begin());
       if (c->p.n_classes == 0) {
-        TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc, c->S, g, m, sweep, nullptr,
-                                           nullptr, hh, ro, c->stream));
+        TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc, c->S, g, m, sweep, list,
+                                           count, hh, ro, c->stream));
       } else {
         const ClassLists cl{c->cls_count, c->cls_list};
         TCA_CK(launch_classify(c->p.Lc_classes, c->p.n_classes, g, c->p.seed, sweep, cl,
@@ -293,14 +259,68 @@ int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* l
       }
       TCA_CK(pr.end(0));
       TCA_CK(pr.begin());
-      TCA_CK(launch_tridiag_eig(c->ld, 2 * hh, ro, T[s], c->p.mu, c->F, nullptr, 0, c->stream));
+      TCA_CK(launch_tridiag_eig(c->ld, 2 * hh, ro, T[s], c->p.mu, c->F, nullptr, 0, c->stream,
+                                list, count));
       TCA_CK(pr.end(1));
+      if (collect) {
+        const int64_t r = row0 + ((int64_t)s * 4 + K) * hh;
+        TCA_CK(sg_block_collect(c->S, g, c->p.Lc, m, sweep, T[s], collect->dm, c->F,
+                                collect->X.p + r * collect->dm.n_in, collect->y.p + r,
+                                c->stream));
+      }
       TCA_CK(pr.begin());
       TCA_CK(launch_decide(c->S, c->F, g, m, sweep, T[s], c->p.Lc, c->p.Lc_classes,
-                           c->p.n_classes, K, dlog.p ? dlog.p + (size_t)s * c->N : nullptr,
+                           c->p.n_classes, K, sg ? c->da.pass.p : nullptr,
+                           sg ? c->da.dS.p : nullptr, dlog ? dlog + (size_t)s * c->N : nullptr,
                            c->counters, c->stream));
       TCA_CK(pr.end(2));
     }
+  }
+  return TCA_OK;
+}
+
+// Totals of a finished call into st (host).
+static int fill_stats(tca_ctx* c, ProfRec& pr, tca_sweep_stats* st) {
+  unsigned long long cnt[4];
+  TCA_CK(hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost));
+  float ms = 0.f;
+  TCA_CK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  memset(st, 0, sizeof(*st));
+  st->accepted = (int64_t)cnt[0];
+  st->near_threshold = (int64_t)cnt[1];
+  st->updates = (int64_t)cnt[2];
+  st->stage1_passed = (int64_t)cnt[3];
+  st->elapsed_ms = ms;
+  for (size_t i = 0; i < pr.used; ++i) {
+    float e = 0.f;
+    TCA_CK(hipEventElapsedTime(&e, c->prof[2 * i], c->prof[2 * i + 1]));
+    switch (pr.kind[i]) {
+      case 0: st->reduce_ms += e; st->reduce_launches += 1; break;
+      case 1: st->eig_ms += e; st->eig_launches += 1; break;
+      case 2: st->decide_ms += e; st->decide_launches += 1; break;
+      default: st->surrogate_ms += e; st->surrogate_launches += 1; break;
+    }
+  }
+  return TCA_OK;
+}
+
+int tca::run_sweeps(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* log,
+                   tca_sweep_stats* st, tca_surrogate* collect, int64_t row0) {
+  DevBuf<tca_update_record> dlog;
+  if (log && nsweeps > 0) {
+    hipError_t e = dlog.alloc((size_t)nsweeps * c->N);
+    if (e != hipSuccess) {
+      set_err("log allocation failed: %s", hipGetErrorString(e));
+      return TCA_E_NOMEM;
+    }
+  }
+  ProfRec pr{c, (c->p.flags & TCA_FLAG_PROFILE) != 0};
+  TCA_CK(launch_zero_u64(c->counters, 4, c->stream));
+  TCA_CK(hipEventRecord(c->ev0, c->stream));
+  int rc = issue_sweeps(c, T, nsweeps, dlog.p, pr, collect, row0);
+  if (rc != TCA_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    return rc;
   }
   TCA_CK(hipEventRecord(c->ev1, c->stream));
   TCA_CK(hipStreamSynchronize(c->stream));
@@ -308,33 +328,27 @@ int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* l
   if (log && nsweeps > 0)
     TCA_CK(hipMemcpy(log, dlog.p, sizeof(tca_update_record) * (size_t)nsweeps * c->N,
                      hipMemcpyDeviceToHost));
-  if (st) {
-    unsigned long long cnt[4];
-    TCA_CK(hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost));
-    float ms = 0.f;
-    TCA_CK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    st->accepted = (int64_t)cnt[0];
-    st->near_threshold = (int64_t)cnt[1];
-    st->updates = (int64_t)cnt[2];
-    st->elapsed_ms = ms;
-    st->reduce_ms = st->eig_ms = st->decide_ms = 0.0;
-    st->reduce_launches = st->eig_launches = st->decide_launches = 0;
-    for (size_t i = 0; i < pr.used; ++i) {
-      float e = 0.f;
-      TCA_CK(hipEventElapsedTime(&e, c->prof[2 * i], c->prof[2 * i + 1]));
-      if (pr.kind[i] == 0) {
-        st->reduce_ms += e;
-        st->reduce_launches += 1;
-      } else if (pr.kind[i] == 1) {
-        st->eig_ms += e;
-        st->eig_launches += 1;
-      } else {
-        st->decide_ms += e;
-        st->decide_launches += 1;
-      }
-    }
-  }
+  if (st) return fill_stats(c, pr, st);
   return TCA_OK;
+}
+
+int tca::check_temps(const double* T, int32_t nsweeps) {
+  if (!T) TCA_INVAL("T is NULL");
+  if (nsweeps < 0) TCA_INVAL("nsweeps < 0");
+  for (int s = 0; s < nsweeps; ++s)
+    if (!is_fin(T[s]) || T[s] <= 0.0) TCA_INVAL("temperatures must be finite and > 0");
+  return TCA_OK;
+}
+
+extern "C" {
+
+int tca_sweep(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* log,
+              tca_sweep_stats* st) {
+  g_err[0] = 0;
+  if (!c) TCA_INVAL("NULL context");
+  const int rc = check_temps(T, nsweeps);
+  if (rc != TCA_OK) return rc;
+  return run_sweeps(c, T, nsweeps, log, st, nullptr, 0);
 }
 
 int tca_cluster_eigvals(tca_ctx* c, const int32_t* sites, const int32_t* Lc,

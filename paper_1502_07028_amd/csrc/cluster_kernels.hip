@@ -139,9 +139,16 @@ __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restr
                                                            const int32_t* __restrict__ nmat,
                                                            double T, double mu,
                                                            double* __restrict__ F,
-                                                           double* __restrict__ ev, int ev_ld) {
+                                                           double* __restrict__ ev, int ev_ld,
+                                                           const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ count) {
   __shared__ double red[NTHR / 64];
-  const int mat = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  int mat = blockIdx.x;
+  if (list != nullptr) {
+    if ((int)(blockIdx.x >> 1) >= *count) return;
+    mat = 2 * list[blockIdx.x >> 1] + (blockIdx.x & 1);
+  }
   const int n = nmat[mat];
   const double* d = D + (size_t)mat * ld;
   const double* e2 = E2 + (size_t)mat * ld;
@@ -227,16 +234,18 @@ hipError_t launch_heevals_reduce(int precision, int n, const double* A, int batc
 }
 
 hipError_t launch_tridiag_eig(int nmax, int nmats, ReduceOut in, double T, double mu, double* F,
-                              double* ev, int ev_ld, hipStream_t st) {
+                              double* ev, int ev_ld, hipStream_t st, const int32_t* list,
+                              const int32_t* count) {
   if (nmats <= 0) return hipSuccess;
   if (nmax <= 64)
-    hipLaunchKernelGGL(tridiag_eig_kernel<64>, dim3(nmats), dim3(64), 0, st, in.D, in.E2, in.ld, in.nmat, T, mu, F, ev, ev_ld);
+    hipLaunchKernelGGL(tridiag_eig_kernel<64>, dim3(nmats), dim3(64), 0, st, in.D, in.E2, in.ld,
+                       in.nmat, T, mu, F, ev, ev_ld, list, count);
   else if (nmax <= 128)
-    hipLaunchKernelGGL(tridiag_eig_kernel<128>, dim3(nmats), dim3(128), 0, st, in.D, in.E2, in.ld, in.nmat, T, mu, F, ev,
-                       ev_ld);
+    hipLaunchKernelGGL(tridiag_eig_kernel<128>, dim3(nmats), dim3(128), 0, st, in.D, in.E2, in.ld,
+                       in.nmat, T, mu, F, ev, ev_ld, list, count);
   else if (nmax <= 256)
-    hipLaunchKernelGGL(tridiag_eig_kernel<256>, dim3(nmats), dim3(256), 0, st, in.D, in.E2, in.ld, in.nmat, T, mu, F, ev,
-                       ev_ld);
+    hipLaunchKernelGGL(tridiag_eig_kernel<256>, dim3(nmats), dim3(256), 0, st, in.D, in.E2, in.ld,
+                       in.nmat, T, mu, F, ev, ev_ld, list, count);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -56,17 +56,21 @@ hipError_t launch_cluster_sites_reduce(int precision, int Lc, const double* S, i
 hipError_t launch_heevals_reduce(int precision, int n, const double* A, int batch, ReduceOut out,
                                  hipStream_t st);
 
-// eigenvalues (optional) and grand potential F (optional) of nmats tridiagonals
+// eigenvalues (optional) and grand potential F (optional) of nmats tridiagonals;
+// with list/count, only matrices 2*list[i] and 2*list[i]+1, i < *count
 hipError_t launch_tridiag_eig(int nmax, int nmats, ReduceOut in, double T, double mu, double* F,
-                              double* ev, int ev_ld, hipStream_t st);
+                              double* ev, int ev_ld, hipStream_t st,
+                              const int32_t* list = nullptr, const int32_t* count = nullptr);
 
 hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g, uint64_t seed,
                            uint64_t sweep, ClassLists cl, hipStream_t st);
 
+// pass/dS: stage-1 flags and surrogate values of delayed acceptance, or nullptr
 hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m,
                          uint64_t sweep, double T, int Lc_fixed, const int32_t* classes_Lc,
-                         int n_classes, int K, tca_update_record* log_dev,
-                         unsigned long long* counters, hipStream_t st);
+                         int n_classes, int K, const uint8_t* pass, const float* dS,
+                         tca_update_record* log_dev, unsigned long long* counters,
+                         hipStream_t st);
 
 hipError_t launch_init_spins(double* S, int L, int kind, uint64_t seed, hipStream_t st);
 

@@ -43,17 +43,24 @@ __device__ __attribute__((noinline)) double classical_delta(const double* S, int
 // J_AF != 0 the sites are processed by anti-diagonals i + j = const of the
 // block: every site is decided after both of those neighbours, exactly as in
 // the sequential order.  With J_AF == 0 all decisions are independent.
+//
+// With delayed acceptance (pass != nullptr) only clusters that passed the
+// surrogate stage were solved exactly; the others are rejected, and a passing
+// one is accepted iff ln u < -dE/T + min(0, -dS_r/T) - min(0, -dS_f/T)
+// (Christen & Fox), dS_f/dS_r the surrogate on the move and its reverse.
 __global__ __launch_bounds__(1024) void decide_kernel(double* S,
                                                       const double* __restrict__ Fpair,
                                                       BlockGeom g, ModelParams m, uint64_t sweep,
                                                       double T, int Lc_fixed, int4 classes,
                                                       int n_classes, int K,
+                                                      const uint8_t* __restrict__ pass,
+                                                      const float* __restrict__ dS,
                                                       tca_update_record* __restrict__ logbuf,
                                                       unsigned long long* __restrict__ counters) {
   const int h = g.h, L = g.L;
   const bool wave = (m.JAF != 0.0);
   const int ndiag = wave ? 2 * h - 1 : 1;
-  unsigned long long nacc = 0, nnear = 0;
+  unsigned long long nacc = 0, nnear = 0, npass = 0;
   for (int dd = 0; dd < ndiag; ++dd) {
     const int lo = wave ? max(0, dd - (h - 1)) : 0;
     const int cnt = wave ? (min(dd, h - 1) - lo + 1) : h * h;
@@ -68,22 +75,44 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S,
       }
       const int c = i + h * j;
       const int px = g.x0 + i, py = g.y0 + j, site = px + L * py;
-      double sn[3];
-      sphere_point(m.seed, sweep, site, kStreamProposal, sn);
-      const double dF = Fpair[2 * c + 1] - Fpair[2 * c];
-      const double dE = dF + classical_delta(S, L, px, py, sn, m.JAF);
       const U64x4 r = philox4x64_10(m.seed, 0, sweep, site, kStreamMetropolis, 0);
       const double u = u53(r.w0);
-      const bool acc = (dE <= 0.0) || (u < exp(-dE / T));
-      bool near = false;
-      if (u > 0.0) near = fabs(dE + T * log(u)) <= 1e-9 * fmax(fabs(dE), 1e-3);
-      if (acc) {
-        S[3 * site + 0] = sn[0];
-        S[3 * site + 1] = sn[1];
-        S[3 * site + 2] = sn[2];
+      const bool stage1 = (pass == nullptr) || (pass[c] != 0);
+      float dSf = 0.0f, dSr = 0.0f;
+      bool near1 = false;
+      if (pass != nullptr) {
+        dSf = dS[2 * c];
+        dSr = dS[2 * c + 1];
+        const double u1 = u53(r.w1);
+        if (u1 > 0.0)
+          near1 = fabs(T * (log(u1) - fmin(0.0, -(double)dSf / T))) <=
+                  1e-9 * fmax(fabs((double)dSf), 1e-3);
+      }
+      double dF = __builtin_nan(""), dE = __builtin_nan("");
+      bool acc = false, near = false;
+      if (stage1) {
+        double sn[3];
+        sphere_point(m.seed, sweep, site, kStreamProposal, sn);
+        dF = Fpair[2 * c + 1] - Fpair[2 * c];
+        dE = dF + classical_delta(S, L, px, py, sn, m.JAF);
+        if (pass == nullptr) {
+          acc = (dE <= 0.0) || (u < exp(-dE / T));
+          if (u > 0.0) near = fabs(dE + T * log(u)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+        } else {
+          const double rhs =
+              -dE / T + fmin(0.0, -(double)dSr / T) - fmin(0.0, -(double)dSf / T);
+          acc = (u <= 0.0) || (log(u) < rhs);
+          if (u > 0.0) near = fabs(T * (log(u) - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+        }
+        if (acc) {
+          S[3 * site + 0] = sn[0];
+          S[3 * site + 1] = sn[1];
+          S[3 * site + 2] = sn[2];
+        }
       }
       nacc += acc;
       nnear += near;
+      npass += stage1;
       if (logbuf != nullptr) {
         int Lc = Lc_fixed;
         if (n_classes > 0) {
@@ -94,10 +123,12 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S,
         rec.site = site;
         rec.Lc = (int16_t)Lc;
         rec.accept = acc ? 1 : 0;
-        rec.flags = near ? 1 : 0;
+        rec.flags = (uint8_t)((near ? 1 : 0) | (stage1 ? 2 : 0) | (near1 ? 4 : 0));
         rec.dF = dF;
         rec.dE = dE;
         rec.u = u;
+        rec.dS_f = dSf;
+        rec.dS_r = dSr;
         logbuf[(size_t)K * h * h + c] = rec;
       }
     }
@@ -105,6 +136,7 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S,
   }
   if (nacc) atomicAdd(&counters[0], nacc);
   if (nnear) atomicAdd(&counters[1], nnear);
+  if (npass) atomicAdd(&counters[3], npass);
   if (threadIdx.x == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
 }
 
@@ -209,11 +241,12 @@ hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g
 
 hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m,
                          uint64_t sweep, double T, int Lc_fixed, const int32_t* classes_Lc,
-                         int n_classes, int K, tca_update_record* log_dev,
-                         unsigned long long* counters, hipStream_t st) {
+                         int n_classes, int K, const uint8_t* pass, const float* dS,
+                         tca_update_record* log_dev, unsigned long long* counters,
+                         hipStream_t st) {
   hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, Fpair, g, m, sweep, T,
-                     Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, K, log_dev,
-                     counters);
+                     Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, K, pass, dS,
+                     log_dev, counters);
   return hipGetLastError();
 }
 

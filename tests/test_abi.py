@@ -38,7 +38,7 @@ def test_struct_layouts_match():
     import paper_1502_07028_amd as tca
     assert tca.tca_abi_sizes() == (ctypes.sizeof(tca.tca_params), ctypes.sizeof(tca.tca_update_record),
                                    ctypes.sizeof(tca.tca_sweep_stats))
-    assert ctypes.sizeof(tca.tca_update_record) == 32
+    assert ctypes.sizeof(tca.tca_update_record) == 40
 
 
 @pytest.mark.parametrize("kw,msg", [
