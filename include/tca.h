@@ -54,7 +54,11 @@ typedef enum {
 enum { TCA_FP64 = 0, TCA_MIXED = 1 };  /* precision of the tridiagonal reduction */
 enum { TCA_INIT_RANDOM = 0, TCA_INIT_FERRO = 1, TCA_INIT_NEEL = 2, TCA_INIT_USER = 3 };
 /* tca_params.flags bits */
-enum { TCA_FLAG_PROFILE = 1 };  /* time every kernel launch of a sweep with HIP events */
+enum {
+  TCA_FLAG_PROFILE = 1,      /* time every kernel launch of a sweep with HIP events */
+  TCA_FLAG_NO_GRAPH = 2,     /* issue every launch directly instead of replaying a captured sweep */
+  TCA_FLAG_NO_AUTOTUNE = 4,  /* keep the default reducer variants (no timing at init) */
+};
 
 typedef struct {
   int32_t abi_version;   /* must be TCA_ABI_VERSION */
@@ -112,9 +116,17 @@ typedef struct tca_surrogate tca_surrogate;
  *   p          host; validated (TCA_E_INVAL on a bad size, precision or flag)
  *   spins_xyz  host N x 3 initial spins when p->init == TCA_INIT_USER (each
  *              |S| within 1e-12 of 1, else TCA_E_INVAL), otherwise ignored
- *   hip_stream hipStream_t to issue all work on, NULL = the null stream
+ *   hip_stream hipStream_t to issue all work on; NULL: a stream the context
+ *              creates and owns (default priority)
  *   out        receives the context (NULL on failure)
- * Random initial spins are uniform on the sphere (Philox stream 3). */
+ * Random initial spins are uniform on the sphere (Philox stream 3).
+ * Unless TCA_FLAG_NO_AUTOTUNE is set, the first context of the process that
+ * uses a cluster size (per precision) times every reducer variant of that
+ * size on its own block-0 clusters and records the fastest for the process
+ * (tca_tuning_report shows the timings).  Sweeps without a log, collection or
+ * profiling are captured once as a HIP graph and replayed per sweep (the
+ * kernels read the sweep counter and T from device memory) unless
+ * TCA_FLAG_NO_GRAPH is set. */
 int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_stream,
                      tca_ctx** out);
 
@@ -258,6 +270,10 @@ int tca_surrogate_eval(tca_surrogate* s, const float* X, int32_t rows, int32_t b
  * Philox block.  The context keeps a pointer: the surrogate must outlive the
  * attachment. */
 int tca_attach_surrogate(tca_ctx* c, tca_surrogate* s);
+
+/* Text of the autotuner's timings and choices for this context's cluster
+ * sizes (host buf of len bytes, NUL-terminated, truncated if needed). */
+int tca_tuning_report(tca_ctx* c, char* buf, int32_t len);
 
 /* Release the context and its device memory (NULL is accepted). */
 int tca_destroy(tca_ctx* c);

@@ -18,7 +18,7 @@ TCA_ABI_VERSION = 2
 TCA_OK, TCA_E_INVAL, TCA_E_NOMEM, TCA_E_DEVICE, TCA_E_UNSUPPORTED = 0, -1, -2, -3, -4
 TCA_FP64, TCA_MIXED = 0, 1
 TCA_INIT_RANDOM, TCA_INIT_FERRO, TCA_INIT_NEEL, TCA_INIT_USER = 0, 1, 2, 3
-TCA_FLAG_PROFILE = 1
+TCA_FLAG_PROFILE, TCA_FLAG_NO_GRAPH, TCA_FLAG_NO_AUTOTUNE = 1, 2, 4
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
@@ -88,6 +88,7 @@ _SIGS = {
     "tca_surrogate_adam_step": [_P, _F, ctypes.c_float],
     "tca_surrogate_eval": [_P, _F, ctypes.c_int32, ctypes.c_int32, _F],
     "tca_attach_surrogate": [_P, _P],
+    "tca_tuning_report": [_P, ctypes.c_char_p, ctypes.c_int32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -166,6 +167,12 @@ def tca_init_lattice(params, spins=None, stream=None):
     _check(_lib.tca_init_lattice(ctypes.byref(params), _dptr(sp), stream, ctypes.byref(h)),
            "tca_init_lattice")
     return h.value
+
+
+def tca_tuning_report(ctx):
+    buf = ctypes.create_string_buffer(4096)
+    _check(_lib.tca_tuning_report(ctx, buf, len(buf)), "tca_tuning_report")
+    return buf.value.decode()
 
 
 def tca_destroy(ctx):
@@ -254,6 +261,9 @@ class Lattice:
 
     def sweep(self, T, log=False):
         return tca_sweep(self.ctx, T, log=log, N=self.N)
+
+    def tuning_report(self):
+        return tca_tuning_report(self.ctx)
 
     def attach(self, surrogate):
         """Use a Surrogate as the first stage of delayed acceptance (None: plain)."""

@@ -13,6 +13,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <string>
 #include <mutex>
 #include <vector>
 
@@ -80,6 +82,11 @@ static void free_ctx(tca_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->prof) (void)hipEventDestroy(e);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->sched_base) (void)hipFree(c->sched_base);
+  if (c->sched_idx) (void)hipFree(c->sched_idx);
+  if (c->sched_T) (void)hipFree(c->sched_T);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -87,7 +94,89 @@ static ModelParams model_of(const tca_ctx* c) {
   return ModelParams{c->p.t, c->p.JH, c->p.JAF, c->p.mu, c->p.seed};
 }
 
+// ---------------------------------------------------------------- autotuner
+// Reducer variants are timed once per process and (dimension class,
+// precision), on the clusters of block 0 of the first context that needs
+// them: one warm-up launch and three timed launches of every variant, the
+// fastest recorded for the process.
+static std::mutex g_tune_mu;
+static bool g_tuned[2][kNumReducerClasses];
+static std::atomic<int> g_tune_gen{0};
+static std::string g_tune_log[2][kNumReducerClasses];
+
+int tca::tuning_generation() { return g_tune_gen.load(); }
+
+static int autotune(tca_ctx* c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int sizes[4], ns = 0;
+  if (c->p.n_classes == 0) {
+    sizes[ns++] = c->p.Lc;
+  } else {
+    for (int k = 0; k < c->p.n_classes; ++k) sizes[ns++] = c->p.Lc_classes[k];
+  }
+  const int prec = c->p.precision == TCA_MIXED ? 1 : 0;
+  const int hh = c->h * c->h;
+  const BlockGeom g{c->p.L, c->h, 0, 0};
+  const ReduceOut ro{c->D, c->E2, c->ld, c->nmat};
+  const ModelParams m = model_of(c);
+  std::string rep;
+  for (int q = 0; q < ns; ++q) {
+    const int n = 2 * sizes[q] * sizes[q];
+    const int cls = reducer_class(n);
+    const int nv = reducer_variants(cls, c->p.precision);
+    if (!g_tuned[prec][cls] && nv > 1) {
+      char line[512];
+      int off = snprintf(line, sizeof(line), "n=%d %s (%d matrices):", n,
+                         prec ? "mixed" : "fp64", 2 * hh);
+      double best_ms = 1e300;
+      int best = 0;
+      for (int v = 0; v < nv; ++v) {
+        TCA_CK(launch_cluster_block_reduce(c->p.precision, sizes[q], c->S, g, m,
+                                           fixed_sweep(0, 1.0), nullptr, nullptr, hh, ro,
+                                           c->stream, v));
+        TCA_CK(hipEventRecord(c->ev0, c->stream));
+        for (int r = 0; r < 3; ++r)
+          TCA_CK(launch_cluster_block_reduce(c->p.precision, sizes[q], c->S, g, m,
+                                             fixed_sweep(0, 1.0), nullptr, nullptr, hh, ro,
+                                             c->stream, v));
+        TCA_CK(hipEventRecord(c->ev1, c->stream));
+        TCA_CK(hipStreamSynchronize(c->stream));
+        float ms = 0.f;
+        TCA_CK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        const double per = ms / 3.0;
+        off += snprintf(line + off, sizeof(line) - (size_t)off, " %s %.3f ms;",
+                        reducer_name(cls, c->p.precision, v), per);
+        if (per < best_ms) {
+          best_ms = per;
+          best = v;
+        }
+      }
+      snprintf(line + off, sizeof(line) - (size_t)off, " -> %s",
+               reducer_name(cls, c->p.precision, best));
+      set_reducer_choice(cls, c->p.precision, best);
+      g_tuned[prec][cls] = true;
+      g_tune_log[prec][cls] = line;
+      g_tune_gen.fetch_add(1);
+    } else if (!g_tuned[prec][cls]) {
+      g_tune_log[prec][cls] = "n=" + std::to_string(n) + (prec ? " mixed" : " fp64") +
+                              ": single variant " + reducer_name(cls, c->p.precision, 0);
+    }
+    rep += g_tune_log[prec][cls] + "\n";
+  }
+  c->tune_report = rep;
+  return TCA_OK;
+}
+
 extern "C" {
+
+int tca_tuning_report(tca_ctx* c, char* buf, int32_t len) {
+  g_err[0] = 0;
+  if (!c || !buf || len < 1) TCA_INVAL("NULL argument or len < 1");
+  const size_t n = c->tune_report.size() < (size_t)(len - 1) ? c->tune_report.size() : (size_t)(len - 1);
+  memcpy(buf, c->tune_report.data(), n);
+  buf[n] = 0;
+  return TCA_OK;
+}
 
 const char* tca_strerror(int s) {
   switch (s) {
@@ -126,7 +215,8 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
       TCA_INVAL("every size class must satisfy 2 <= Lc <= min(10, L/2+1)");
   if (p->precision != TCA_FP64 && p->precision != TCA_MIXED) TCA_INVAL("bad precision");
   if (p->init < TCA_INIT_RANDOM || p->init > TCA_INIT_USER) TCA_INVAL("bad init");
-  if (p->flags & ~TCA_FLAG_PROFILE) TCA_INVAL("unknown flag bits");
+  if (p->flags & ~(TCA_FLAG_PROFILE | TCA_FLAG_NO_GRAPH | TCA_FLAG_NO_AUTOTUNE))
+    TCA_INVAL("unknown flag bits");
   if (!is_fin(p->t) || !is_fin(p->JH) || !is_fin(p->JAF) || !is_fin(p->mu))
     TCA_INVAL("model parameters must be finite");
   const int N = p->L * p->L;
@@ -141,6 +231,14 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
   }
   c->p = *p;
   c->stream = (hipStream_t)hip_stream;
+  if (c->stream == nullptr) {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      set_err("stream creation failed");
+      delete c;
+      return TCA_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
   c->N = N;
   c->h = p->L / 2;
   const size_t hh = (size_t)c->h * c->h;
@@ -156,6 +254,8 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
   if (e == hipSuccess) e = hipMalloc((void**)&c->cls_count, sizeof(int32_t) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&c->cls_list, sizeof(int32_t) * 4 * hh);
   if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->sched_base, sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->sched_idx, sizeof(int32_t));
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
   if (e != hipSuccess) {
@@ -173,6 +273,13 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
     set_err("initialization failed: %s", hipGetErrorString(e));
     free_ctx(c);
     return TCA_E_DEVICE;
+  }
+  if (!(p->flags & TCA_FLAG_NO_AUTOTUNE)) {
+    const int rc = autotune(c);
+    if (rc != TCA_OK) {
+      free_ctx(c);
+      return rc;
+    }
   }
   *out = c;
   return TCA_OK;
@@ -203,79 +310,68 @@ int tca_get_sweep_counter(tca_ctx* c, uint64_t* sc) {
 
 }  // extern "C"
 
-// Issue nsweeps sweeps on the context's stream (no synchronization).  With a
-// surrogate attached, each block first runs the delayed-acceptance stage 1
-// (features of the forward and reverse moves, BF16 MLP, pass flags and the
-// compacted list of survivors) and only the survivors are solved exactly.
-// With `collect`, every update's (features, dF) row is appended to the
-// surrogate's dataset starting at row `row0` (plain sweeps only).
-static int issue_sweeps(tca_ctx* c, const double* T, int nsweeps, tca_update_record* dlog,
-                     ProfRec& pr, tca_surrogate* collect, int64_t row0) {
+// Issue one sweep on the context's stream (no synchronization), reading the
+// sweep counter and temperature through `sr`.  With a surrogate attached, each
+// block first runs the delayed-acceptance stage 1 (features of the forward and
+// reverse moves, BF16 MLP, pass flags and the compacted list of survivors) and
+// only the survivors are solved exactly.  With `collect`, every update's
+// (features, dF) row is appended to the surrogate's dataset from row `row0` on
+// (plain sweeps only).  The call ends by advancing the device sweep index.
+static int issue_sweep(tca_ctx* c, SweepRef sr, int32_t* idx, tca_update_record* dlog,
+                       ProfRec& pr, tca_surrogate* collect, int64_t row0) {
   const int L = c->p.L, h = c->h, hh = h * h;
   const ModelParams m = model_of(c);
   tca_surrogate* sg = collect ? nullptr : c->sg;
-  if (sg && sg->bf16_stale) {
-    TCA_CK(sg_to_bf16(sg->W.p, sg->dm, sg->W1b.p, sg->W2b.p, c->stream));
-    sg->bf16_stale = false;
-  }
-  for (int s = 0; s < nsweeps; ++s) {
-    const uint64_t sweep = c->sweep_counter + (uint64_t)s;
-    for (int K = 0; K < 4; ++K) {
-      const BlockGeom g{L, h, h * (K & 1), h * (K >> 1)};
-      const ReduceOut ro{c->D, c->E2, c->ld, c->nmat};
-      const int32_t* list = nullptr;
-      const int32_t* count = nullptr;
-      if (sg) {
-        TCA_CK(pr.begin());
-        TCA_CK(sg_block_features(c->S, g, c->p.Lc, m, sweep, T[s], sg->dm, c->da.Fin.p,
-                                 c->stream));
-        TCA_CK(sg_infer_bf16(c->da.Fin.p, 2 * hh, sg->W.p, sg->W1b.p, sg->W2b.p, sg->dm,
-                             SgInferBufs{c->da.H1.p, c->da.H2.p}, c->da.dS.p, c->stream));
-        TCA_CK(sg_stage1(c->da.dS.p, g, m, sweep, T[s], c->da.pass.p, c->da.count.p,
-                         c->da.list.p, c->stream));
-        TCA_CK(pr.end(3));
-        list = c->da.list.p;
-        count = c->da.count.p;
-      }
+  for (int K = 0; K < 4; ++K) {
+    const BlockGeom g{L, h, h * (K & 1), h * (K >> 1)};
+    const ReduceOut ro{c->D, c->E2, c->ld, c->nmat};
+    const int32_t* list = nullptr;
+    const int32_t* count = nullptr;
+    if (sg) {
       TCA_CK(pr.begin());
-      if (c->p.n_classes == 0) {
-        TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc, c->S, g, m, sweep, list,
-                                           count, hh, ro, c->stream));
-      } else {
-        const ClassLists cl{c->cls_count, c->cls_list};
-        TCA_CK(launch_classify(c->p.Lc_classes, c->p.n_classes, g, c->p.seed, sweep, cl,
-                               c->stream));
-        // largest clusters first so the longest workgroups start earliest
-        int order[4] = {0, 1, 2, 3};
-        for (int a = 0; a < c->p.n_classes; ++a)
-          for (int b = a + 1; b < c->p.n_classes; ++b)
-            if (c->p.Lc_classes[order[b]] > c->p.Lc_classes[order[a]]) std::swap(order[a], order[b]);
-        for (int a = 0; a < c->p.n_classes; ++a) {
-          const int k = order[a];
-          TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc_classes[k], c->S, g, m, sweep,
-                                             c->cls_list + (size_t)k * hh, c->cls_count + k, hh,
-                                             ro, c->stream));
-        }
-      }
-      TCA_CK(pr.end(0));
-      TCA_CK(pr.begin());
-      TCA_CK(launch_tridiag_eig(c->ld, 2 * hh, ro, T[s], c->p.mu, c->F, nullptr, 0, c->stream,
-                                list, count));
-      TCA_CK(pr.end(1));
-      if (collect) {
-        const int64_t r = row0 + ((int64_t)s * 4 + K) * hh;
-        TCA_CK(sg_block_collect(c->S, g, c->p.Lc, m, sweep, T[s], collect->dm, c->F,
-                                collect->X.p + r * collect->dm.n_in, collect->y.p + r,
-                                c->stream));
-      }
-      TCA_CK(pr.begin());
-      TCA_CK(launch_decide(c->S, c->F, g, m, sweep, T[s], c->p.Lc, c->p.Lc_classes,
-                           c->p.n_classes, K, sg ? c->da.pass.p : nullptr,
-                           sg ? c->da.dS.p : nullptr, dlog ? dlog + (size_t)s * c->N : nullptr,
-                           c->counters, c->stream));
-      TCA_CK(pr.end(2));
+      TCA_CK(sg_block_features(c->S, g, c->p.Lc, m, sr, sg->dm, c->da.Fin.p, c->stream));
+      TCA_CK(sg_infer_bf16(c->da.Fin.p, 2 * hh, sg->W.p, sg->W1b.p, sg->W2b.p, sg->dm,
+                           SgInferBufs{c->da.H1.p, c->da.H2.p}, c->da.dS.p, c->stream));
+      TCA_CK(sg_stage1(c->da.dS.p, g, m, sr, c->da.pass.p, c->da.count.p, c->da.list.p,
+                       c->stream));
+      TCA_CK(pr.end(3));
+      list = c->da.list.p;
+      count = c->da.count.p;
     }
+    TCA_CK(pr.begin());
+    if (c->p.n_classes == 0) {
+      TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc, c->S, g, m, sr, list, count,
+                                         hh, ro, c->stream));
+    } else {
+      const ClassLists cl{c->cls_count, c->cls_list};
+      TCA_CK(launch_classify(c->p.Lc_classes, c->p.n_classes, g, c->p.seed, sr, cl, c->stream));
+      // largest clusters first so the longest workgroups start earliest
+      int order[4] = {0, 1, 2, 3};
+      for (int a = 0; a < c->p.n_classes; ++a)
+        for (int b = a + 1; b < c->p.n_classes; ++b)
+          if (c->p.Lc_classes[order[b]] > c->p.Lc_classes[order[a]]) std::swap(order[a], order[b]);
+      for (int a = 0; a < c->p.n_classes; ++a) {
+        const int k = order[a];
+        TCA_CK(launch_cluster_block_reduce(c->p.precision, c->p.Lc_classes[k], c->S, g, m, sr,
+                                           c->cls_list + (size_t)k * hh, c->cls_count + k, hh, ro,
+                                           c->stream));
+      }
+    }
+    TCA_CK(pr.end(0));
+    TCA_CK(pr.begin());
+    TCA_CK(launch_tridiag_eig(c->ld, 2 * hh, ro, sr, c->p.mu, c->F, nullptr, 0, c->stream, list,
+                              count));
+    TCA_CK(pr.end(1));
+    if (collect)
+      TCA_CK(sg_block_collect(c->S, g, K, c->p.Lc, m, sr, collect->dm, c->F, collect->X.p,
+                              collect->y.p, row0, c->stream));
+    TCA_CK(pr.begin());
+    TCA_CK(launch_decide(c->S, c->F, g, m, sr, c->p.Lc, c->p.Lc_classes, c->p.n_classes, K,
+                         sg ? c->da.pass.p : nullptr, sg ? c->da.dS.p : nullptr, dlog, c->counters,
+                         c->stream));
+    TCA_CK(pr.end(2));
   }
+  TCA_CK(launch_advance(idx, c->stream));
   return TCA_OK;
 }
 
@@ -304,8 +400,16 @@ static int fill_stats(tca_ctx* c, ProfRec& pr, tca_sweep_stats* st) {
   return TCA_OK;
 }
 
+// Key of the captured sweep graph: everything a captured launch depends on.
+static void graph_key(const tca_ctx* c, uintptr_t key[4]) {
+  key[0] = (uintptr_t)c->sg;
+  key[1] = (uintptr_t)c->sched_T;
+  key[2] = (uintptr_t)tuning_generation();
+  key[3] = c->sg ? (uintptr_t)c->da.H1.p : 0;
+}
+
 int tca::run_sweeps(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* log,
-                   tca_sweep_stats* st, tca_surrogate* collect, int64_t row0) {
+                    tca_sweep_stats* st, tca_surrogate* collect, int64_t row0) {
   DevBuf<tca_update_record> dlog;
   if (log && nsweeps > 0) {
     hipError_t e = dlog.alloc((size_t)nsweeps * c->N);
@@ -314,13 +418,64 @@ int tca::run_sweeps(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_rec
       return TCA_E_NOMEM;
     }
   }
+  if (nsweeps > c->sched_cap) {
+    TCA_CK(hipStreamSynchronize(c->stream));
+    if (c->sched_T) TCA_CK(hipFree(c->sched_T));
+    c->sched_T = nullptr;
+    c->sched_cap = 0;
+    TCA_CK(hipMalloc((void**)&c->sched_T, sizeof(double) * (size_t)nsweeps));
+    c->sched_cap = nsweeps;
+  }
+  tca_surrogate* sg = collect ? nullptr : c->sg;
+  if (sg && sg->bf16_stale) {
+    TCA_CK(sg_to_bf16(sg->W.p, sg->dm, sg->W1b.p, sg->W2b.p, c->stream));
+    sg->bf16_stale = false;
+  }
   ProfRec pr{c, (c->p.flags & TCA_FLAG_PROFILE) != 0};
+  if (nsweeps > 0) {
+    TCA_CK(hipMemcpyAsync(c->sched_T, T, sizeof(double) * (size_t)nsweeps, hipMemcpyHostToDevice,
+                          c->stream));
+    c->sched_host_base = c->sweep_counter;
+    TCA_CK(hipMemcpyAsync(c->sched_base, &c->sched_host_base, sizeof(uint64_t),
+                          hipMemcpyHostToDevice, c->stream));
+  }
+  TCA_CK(launch_zero_i32(c->sched_idx, 1, c->stream));
   TCA_CK(launch_zero_u64(c->counters, 4, c->stream));
+  const SweepRef sr{c->sched_base, c->sched_idx, c->sched_T, 0, 0.0};
+  const bool graph = !log && !collect && !pr.on && !(c->p.flags & TCA_FLAG_NO_GRAPH);
+  if (graph && nsweeps > 0) {
+    uintptr_t key[4];
+    graph_key(c, key);
+    if (!c->graph_exec || memcmp(key, c->graph_key, sizeof(key)) != 0) {
+      if (c->graph_exec) TCA_CK(hipGraphExecDestroy(c->graph_exec));
+      c->graph_exec = nullptr;
+      TCA_CK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+      const int rc = issue_sweep(c, sr, c->sched_idx, nullptr, pr, nullptr, 0);
+      hipGraph_t gr = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->stream, &gr);
+      if (rc != TCA_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      TCA_CK(ec);
+      const hipError_t ei = hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      TCA_CK(ei);
+      memcpy(c->graph_key, key, sizeof(key));
+      c->graph_captures += 1;
+    }
+  }
   TCA_CK(hipEventRecord(c->ev0, c->stream));
-  int rc = issue_sweeps(c, T, nsweeps, dlog.p, pr, collect, row0);
-  if (rc != TCA_OK) {
-    (void)hipStreamSynchronize(c->stream);
-    return rc;
+  for (int s = 0; s < nsweeps; ++s) {
+    if (graph) {
+      TCA_CK(hipGraphLaunch(c->graph_exec, c->stream));
+    } else {
+      const int rc = issue_sweep(c, sr, c->sched_idx, dlog.p, pr, collect, row0);
+      if (rc != TCA_OK) {
+        (void)hipStreamSynchronize(c->stream);
+        return rc;
+      }
+    }
   }
   TCA_CK(hipEventRecord(c->ev1, c->stream));
   TCA_CK(hipStreamSynchronize(c->stream));
@@ -396,7 +551,8 @@ int tca_cluster_eigvals(tca_ctx* c, const int32_t* sites, const int32_t* Lc,
       TCA_CK(hipMemcpy(dprop.p, hp.data(), sizeof(double) * 3 * k, hipMemcpyHostToDevice));
     TCA_CK(launch_cluster_sites_reduce(c->p.precision, Lv, c->S, L, m, dsites.p,
                                        proposed_xyz ? dprop.p : nullptr, k, ro, c->stream));
-    TCA_CK(launch_tridiag_eig(2 * Lv * Lv, k, ro, 1.0, 0.0, nullptr, dev.p, ld, c->stream));
+    TCA_CK(launch_tridiag_eig(2 * Lv * Lv, k, ro, fixed_sweep(0, 1.0), 0.0, nullptr, dev.p, ld,
+                              c->stream));
     TCA_CK(hipStreamSynchronize(c->stream));
     std::vector<double> tmp((size_t)k * ld);
     TCA_CK(hipMemcpy(tmp.data(), dev.p, sizeof(double) * k * ld, hipMemcpyDeviceToHost));
@@ -468,7 +624,7 @@ int tca_heevals_batched_dev(const double* A, int32_t n, int32_t batch, int32_t p
   const ReduceOut ro{g_ws, g_ws + (size_t)batch * n, n, (int32_t*)(g_ws + (size_t)2 * batch * n)};
   hipStream_t st = (hipStream_t)hip_stream;
   TCA_CK(launch_heevals_reduce(precision, n, A, batch, ro, st));
-  TCA_CK(launch_tridiag_eig(n, batch, ro, T, mu, F, w, n, st));
+  TCA_CK(launch_tridiag_eig(n, batch, ro, fixed_sweep(0, F ? T : 1.0), mu, F, w, n, st));
   return TCA_OK;
 }
 
@@ -492,7 +648,8 @@ int tca_heevals_batched(const double* A, int32_t n, int32_t batch, int32_t preci
   TCA_CK(hipMemcpy(dA.p, A, sizeof(double) * nA, hipMemcpyHostToDevice));
   const ReduceOut ro{dD.p, dE.p, n, dn.p};
   TCA_CK(launch_heevals_reduce(precision, n, dA.p, batch, ro, nullptr));
-  TCA_CK(launch_tridiag_eig(n, batch, ro, F ? T : 1.0, mu, F ? dF.p : nullptr, w ? dw.p : nullptr,
+  TCA_CK(launch_tridiag_eig(n, batch, ro, fixed_sweep(0, F ? T : 1.0), mu, F ? dF.p : nullptr,
+                            w ? dw.p : nullptr,
                             n, nullptr));
   TCA_CK(hipDeviceSynchronize());
   if (w) TCA_CK(hipMemcpy(w, dw.p, sizeof(double) * batch * n, hipMemcpyDeviceToHost));

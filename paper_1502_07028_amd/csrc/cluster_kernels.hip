@@ -14,10 +14,14 @@
 //  tridiag_eig_kernel    eigenvalues + F = sum_i [min(x,0) - T log1p(e^{-|x|/T})]
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+#include <unordered_map>
 #include <type_traits>
 
 #include "internal.hpp"
 #include "reduce_full.hpp"
+#include "reduce_fused.hpp"
 #include "reduce_lower.hpp"
 #include "rng.hpp"
 #include "tridiag.hpp"
@@ -74,26 +78,32 @@ __device__ __forceinline__ void solve_cluster(const double* sp, int Lc, const Mo
   Red::run(n, A, sm, d, e2);
 }
 
+// One workgroup per matrix: matrix 2c is the old and 2c+1 the new cluster c.
+// With a compacted work list (survivors of the first stage, or one size
+// class) the bound is read on the device; the listed items occupy the first
+// workgroups and the rest exit at once.  (A persistent loop around the
+// register-resident reduction makes the compiler spill the matrix, so the
+// reduction kernels keep one item per workgroup.)
 template <class Red, typename R>
 __global__ __launch_bounds__(Red::NT, Red::MINW) void cluster_block_reduce(
-    const double* __restrict__ S, BlockGeom g, int Lc, ModelParams m, uint64_t sweep,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ count, ReduceOut out) {
+    const double* __restrict__ S, BlockGeom g, int Lc, ModelParams m, SweepRef sr,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ count, int max_clusters,
+    ReduceOut out) {
   __shared__ typename Red::Smem sm;
   __shared__ double sp[3 * kMaxLc * kMaxLc];
-  const int ci = blockIdx.x >> 1, which = blockIdx.x & 1;
-  int c = ci;
-  if (list != nullptr) {
-    if (ci >= *count) return;
-    c = list[ci];
-  }
+  const int w = blockIdx.x;
+  if (w >= 2 * (list != nullptr ? *count : max_clusters)) return;
+  const int ci = w >> 1, which = w & 1;
+  const int c = list != nullptr ? list[ci] : ci;
   const int px = g.x0 + c % g.h, py = g.y0 + c / g.h;
   const int site = px + g.L * py;
   gather_spins(S, g.L, px, py, Lc, sp);
   __syncthreads();
-  if (which == 1 && threadIdx.x == 0) sphere_point(m.seed, sweep, site, kStreamProposal, sp);
+  if (which == 1 && threadIdx.x == 0) sphere_point(m.seed, sr.sweep(), site, kStreamProposal, sp);
   __syncthreads();
   const int mat = 2 * c + which;
-  solve_cluster<Red, R>(sp, Lc, m, sm, out.D + (size_t)mat * out.ld, out.E2 + (size_t)mat * out.ld);
+  solve_cluster<Red, R>(sp, Lc, m, sm, out.D + (size_t)mat * out.ld,
+                        out.E2 + (size_t)mat * out.ld);
   if (threadIdx.x == 0) out.nmat[mat] = 2 * Lc * Lc;
 }
 
@@ -114,8 +124,8 @@ __global__ __launch_bounds__(Red::NT, Red::MINW) void cluster_sites_reduce(
 }
 
 template <class Red, typename R>
-__global__ __launch_bounds__(Red::NT, Red::MINW) void heevals_reduce(const double* __restrict__ Ag, int n,
-                                                          ReduceOut out) {
+__global__ __launch_bounds__(Red::NT, Red::MINW) void heevals_reduce(const double* __restrict__ Ag,
+                                                                     int n, ReduceOut out) {
   __shared__ typename Red::Smem sm;
   const int b = blockIdx.x;
   const double* M = Ag + (size_t)b * n * n * 2;
@@ -128,85 +138,169 @@ __global__ __launch_bounds__(Red::NT, Red::MINW) void heevals_reduce(const doubl
   if (threadIdx.x == 0) out.nmat[b] = n;
 }
 
-// One workgroup per tridiagonal: thread j finds eigenvalue j; then the grand
-// potential is reduced in a fixed order.  Every lane of a wavefront walks the
-// same (d, e2) with the same index, so the Sturm loops read them through the
-// scalar cache straight from global memory (read-only in this kernel) and use
-// them as scalar operands.
+// One workgroup per tridiagonal (persistent over the matrices): thread j
+// finds eigenvalues j, j + NTHR, ...; then the grand potential is reduced in
+// a fixed order.  Every lane of a wavefront walks the same (d, e2) with the
+// same index, so the Sturm loops read them through the scalar cache straight
+// from global memory (read-only in this kernel) as scalar operands.
 template <int NTHR>
 __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restrict__ D,
                                                            const double* __restrict__ E2, int ld,
                                                            const int32_t* __restrict__ nmat,
-                                                           double T, double mu,
+                                                           int nmats, SweepRef sr, double mu,
                                                            double* __restrict__ F,
                                                            double* __restrict__ ev, int ev_ld,
                                                            const int32_t* __restrict__ list,
                                                            const int32_t* __restrict__ count) {
   __shared__ double red[NTHR / 64];
   const int tid = threadIdx.x;
-  int mat = blockIdx.x;
-  if (list != nullptr) {
-    if ((int)(blockIdx.x >> 1) >= *count) return;
-    mat = 2 * list[blockIdx.x >> 1] + (blockIdx.x & 1);
-  }
-  const int n = nmat[mat];
-  const double* d = D + (size_t)mat * ld;
-  const double* e2 = E2 + (size_t)mat * ld;
-  const TriBounds B = tri_bounds(n, d, e2);
-  double acc = 0.0;
-  for (int j = tid; j < n; j += NTHR) {
-    const double lam = tri_eigenvalue(n, j, d, e2, B);
-    if (ev != nullptr) ev[(size_t)mat * ev_ld + j] = lam;
-    if (F != nullptr) acc += omega_term(lam, T, mu);
-  }
-  if (F == nullptr) return;
-  acc = wave_total(acc);
-  if ((tid & 63) == 0) red[tid >> 6] = acc;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int w = 0; w < NTHR / 64; ++w) s += red[w];
-    F[mat] = s;
+  const double T = sr.T();
+  const int limit = list != nullptr ? 2 * *count : nmats;
+  for (int w = blockIdx.x; w < limit; w += gridDim.x) {
+    const int mat = list != nullptr ? 2 * list[w >> 1] + (w & 1) : w;
+    const int n = nmat[mat];
+    const double* d = D + (size_t)mat * ld;
+    const double* e2 = E2 + (size_t)mat * ld;
+    const TriBounds B = tri_bounds(n, d, e2);
+    double acc = 0.0;
+    for (int j = tid; j < n; j += NTHR) {
+      const double lam = tri_eigenvalue(n, j, d, e2, B);
+      if (ev != nullptr) ev[(size_t)mat * ev_ld + j] = lam;
+      if (F != nullptr) acc += omega_term(lam, T, mu);
+    }
+    if (F != nullptr) {
+      acc = wave_total(acc);
+      if ((tid & 63) == 0) red[tid >> 6] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int q = 0; q < NTHR / 64; ++q) s += red[q];
+        F[mat] = s;
+      }
+      __syncthreads();
+    }
   }
 }
 
 // -------------------------------------------------------------------------
-// Reducer per (dimension, precision).  Full storage on a TR x TC grid where
-// the whole matrix fits the register file; lower-triangle storage above
+// Reducer variants per (dimension class, precision); the autotuner times them
+// and records the fastest in a process-wide table.  Class k covers
+// n <= kClassMaxN[k].  Full storage on a TR x TC grid where the matrix fits
+// the register file (fused or two-pass step), lower-triangle storage above
 // dimension 128 in FP64.
+constexpr int kClassMaxN[kNumReducerClasses] = {32, 64, 80, 128, 176, 208};
+
 template <typename F>
-static hipError_t dispatch_reducer(int n, int precision, F&& f) {
+static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
   if (precision == TCA_MIXED) {
     using R = float;
-    if (n <= 32) return f(ReduceFull<8, 8, 4, 4, R>{}, R{});
-    if (n <= 64) return f(ReduceFull<16, 16, 4, 4, R>{}, R{});
-    if (n <= 80) return f(ReduceFull<16, 16, 5, 5, R>{}, R{});
-    if (n <= 128) return f(ReduceFull<32, 16, 4, 8, R>{}, R{});
-    if (n <= 176) return f(ReduceFull<32, 16, 6, 11, R>{}, R{});
-    if (n <= 208) return f(ReduceFull<32, 16, 7, 13, R>{}, R{});
+    switch (cls) {
+      case 0: return v == 0 ? f(ReduceFused<8, 8, 4, 4, R>{}, R{}) : f(ReduceFull<8, 8, 4, 4, R>{}, R{});
+      case 1: return v == 0 ? f(ReduceFused<16, 16, 4, 4, R>{}, R{}) : f(ReduceFull<16, 16, 4, 4, R>{}, R{});
+      case 2: return v == 0 ? f(ReduceFused<16, 16, 5, 5, R>{}, R{}) : f(ReduceFull<16, 16, 5, 5, R>{}, R{});
+      case 3:
+        return v == 0 ? f(ReduceFused<32, 16, 4, 8, R>{}, R{})
+               : v == 1 ? f(ReduceFused<32, 16, 4, 8, R, 2>{}, R{})
+                        : f(ReduceFull<32, 16, 4, 8, R>{}, R{});
+      case 4: return v == 0 ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{}) : f(ReduceFull<32, 16, 6, 11, R>{}, R{});
+      case 5: return v == 0 ? f(ReduceFused<32, 16, 7, 13, R, 2>{}, R{}) : f(ReduceFull<32, 16, 7, 13, R>{}, R{});
+    }
   } else {
     using R = double;
-    if (n <= 32) return f(ReduceFull<8, 8, 4, 4, R>{}, R{});
-    if (n <= 64) return f(ReduceFull<16, 16, 4, 4, R>{}, R{});
-    if (n <= 80) return f(ReduceFull<16, 16, 5, 5, R>{}, R{});
-    if (n <= 128) return f(ReduceFull<32, 16, 4, 8, R>{}, R{});
-    if (n <= 176) return f(ReduceLower<16, 11, R>{}, R{});
-    if (n <= 208) return f(ReduceLower<16, 13, R>{}, R{});
+    switch (cls) {
+      case 0: return v == 0 ? f(ReduceFused<8, 8, 4, 4, R>{}, R{}) : f(ReduceFull<8, 8, 4, 4, R>{}, R{});
+      case 1: return v == 0 ? f(ReduceFused<16, 16, 4, 4, R>{}, R{}) : f(ReduceFull<16, 16, 4, 4, R>{}, R{});
+      case 2: return v == 0 ? f(ReduceFused<16, 16, 5, 5, R>{}, R{}) : f(ReduceFull<16, 16, 5, 5, R>{}, R{});
+      case 3: return v == 0 ? f(ReduceFused<32, 16, 4, 8, R>{}, R{}) : f(ReduceFull<32, 16, 4, 8, R>{}, R{});
+      case 4: return f(ReduceLower<16, 11, R>{}, R{});
+      case 5: return f(ReduceLower<16, 13, R>{}, R{});
+    }
   }
   return hipErrorInvalidValue;
 }
 
+static const char* const kVariantNames[2][kNumReducerClasses][3] = {
+    {{"fused 8x8 grid", "two-pass 8x8 grid", nullptr},
+     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
+     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
+     {"fused 32x16 grid", "two-pass 32x16 grid", nullptr},
+     {"lower-triangle 16x16 grid", nullptr, nullptr},
+     {"lower-triangle 16x16 grid", nullptr, nullptr}},
+    {{"fused 8x8 grid", "two-pass 8x8 grid", nullptr},
+     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
+     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
+     {"fused 32x16 grid, 2 workgroups/CU", "fused 32x16 grid, 1 workgroup/CU",
+      "two-pass 32x16 grid"},
+     {"fused 32x16 grid", "two-pass 32x16 grid", nullptr},
+     {"fused 32x16 grid", "two-pass 32x16 grid", nullptr}}};
+
+static std::atomic<int> g_choice[2][kNumReducerClasses];
+
+int reducer_class(int n) {
+  for (int k = 0; k < kNumReducerClasses; ++k)
+    if (n <= kClassMaxN[k]) return k;
+  return -1;
+}
+
+int reducer_variants(int cls, int precision) {
+  int v = 0;
+  while (v < 3 && kVariantNames[precision == TCA_MIXED][cls][v] != nullptr) ++v;
+  return v;
+}
+
+const char* reducer_name(int cls, int precision, int variant) {
+  return kVariantNames[precision == TCA_MIXED][cls][variant];
+}
+
+int reducer_choice(int cls, int precision) { return g_choice[precision == TCA_MIXED][cls].load(); }
+
+void set_reducer_choice(int cls, int precision, int variant) {
+  g_choice[precision == TCA_MIXED][cls].store(variant);
+}
+
+template <typename F>
+static hipError_t dispatch_reducer(int n, int precision, int variant, F&& f) {
+  const int cls = reducer_class(n);
+  if (cls < 0) return hipErrorInvalidValue;
+  int v = variant >= 0 ? variant : reducer_choice(cls, precision);
+  if (v >= reducer_variants(cls, precision)) v = 0;
+  return dispatch_variant(cls, precision, v, f);
+}
+
 bool supported_n(int n) { return n >= 2 && n <= kMaxN; }
 
+// Resident workgroups of a kernel on the current device (cached per kernel).
+static int resident_grid(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(kernel);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  cache[kernel] = cus * per_cu;
+  return cus * per_cu;
+}
+
+static dim3 persistent(int items, int resident) {
+  return dim3((unsigned)(items < resident ? (items > 0 ? items : 1) : resident));
+}
+
 hipError_t launch_cluster_block_reduce(int precision, int Lc, const double* S, BlockGeom g,
-                                       ModelParams m, uint64_t sweep, const int32_t* list,
+                                       ModelParams m, SweepRef sr, const int32_t* list,
                                        const int32_t* count, int max_clusters, ReduceOut out,
-                                       hipStream_t st) {
-  return dispatch_reducer(2 * Lc * Lc, precision, [&](auto red, auto r) -> hipError_t {
+                                       hipStream_t st, int variant) {
+  if (max_clusters <= 0) return hipSuccess;
+  return dispatch_reducer(2 * Lc * Lc, precision, variant, [&](auto red, auto r) -> hipError_t {
     using Red = decltype(red);
     using R = decltype(r);
     hipLaunchKernelGGL((cluster_block_reduce<Red, R>), dim3(2 * max_clusters), dim3(Red::NT), 0,
-                       st, S, g, Lc, m, sweep, list, count, out);
+                       st, S, g, Lc, m, sr, list, count, max_clusters, out);
     return hipGetLastError();
   });
 }
@@ -214,18 +308,20 @@ hipError_t launch_cluster_block_reduce(int precision, int Lc, const double* S, B
 hipError_t launch_cluster_sites_reduce(int precision, int Lc, const double* S, int L,
                                        ModelParams m, const int32_t* sites, const double* prop,
                                        int count, ReduceOut out, hipStream_t st) {
-  return dispatch_reducer(2 * Lc * Lc, precision, [&](auto red, auto r) -> hipError_t {
+  if (count <= 0) return hipSuccess;
+  return dispatch_reducer(2 * Lc * Lc, precision, -1, [&](auto red, auto r) -> hipError_t {
     using Red = decltype(red);
     using R = decltype(r);
-    hipLaunchKernelGGL((cluster_sites_reduce<Red, R>), dim3(count), dim3(Red::NT), 0, st, S, L, Lc,
-                       m, sites, prop, out);
+    hipLaunchKernelGGL((cluster_sites_reduce<Red, R>), dim3(count), dim3(Red::NT), 0, st, S, L,
+                       Lc, m, sites, prop, out);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_heevals_reduce(int precision, int n, const double* A, int batch, ReduceOut out,
-                                 hipStream_t st) {
-  return dispatch_reducer(n, precision, [&](auto red, auto r) -> hipError_t {
+                                 hipStream_t st, int variant) {
+  if (batch <= 0) return hipSuccess;
+  return dispatch_reducer(n, precision, variant, [&](auto red, auto r) -> hipError_t {
     using Red = decltype(red);
     using R = decltype(r);
     hipLaunchKernelGGL((heevals_reduce<Red, R>), dim3(batch), dim3(Red::NT), 0, st, A, n, out);
@@ -233,22 +329,24 @@ hipError_t launch_heevals_reduce(int precision, int n, const double* A, int batc
   });
 }
 
-hipError_t launch_tridiag_eig(int nmax, int nmats, ReduceOut in, double T, double mu, double* F,
-                              double* ev, int ev_ld, hipStream_t st, const int32_t* list,
-                              const int32_t* count) {
-  if (nmats <= 0) return hipSuccess;
-  if (nmax <= 64)
-    hipLaunchKernelGGL(tridiag_eig_kernel<64>, dim3(nmats), dim3(64), 0, st, in.D, in.E2, in.ld,
-                       in.nmat, T, mu, F, ev, ev_ld, list, count);
-  else if (nmax <= 128)
-    hipLaunchKernelGGL(tridiag_eig_kernel<128>, dim3(nmats), dim3(128), 0, st, in.D, in.E2, in.ld,
-                       in.nmat, T, mu, F, ev, ev_ld, list, count);
-  else if (nmax <= 256)
-    hipLaunchKernelGGL(tridiag_eig_kernel<256>, dim3(nmats), dim3(256), 0, st, in.D, in.E2, in.ld,
-                       in.nmat, T, mu, F, ev, ev_ld, list, count);
-  else
-    return hipErrorInvalidValue;
+template <int NTHR>
+static hipError_t eig_launch(int nmats, ReduceOut in, SweepRef sr, double mu, double* F,
+                             double* ev, int ev_ld, hipStream_t st, const int32_t* list,
+                             const int32_t* count) {
+  auto kern = tridiag_eig_kernel<NTHR>;
+  hipLaunchKernelGGL(kern, persistent(nmats, resident_grid((const void*)kern, NTHR)), dim3(NTHR), 0, st,
+                     in.D, in.E2, in.ld, in.nmat, nmats, sr, mu, F, ev, ev_ld, list, count);
   return hipGetLastError();
+}
+
+hipError_t launch_tridiag_eig(int nmax, int nmats, ReduceOut in, SweepRef sr, double mu,
+                              double* F, double* ev, int ev_ld, hipStream_t st,
+                              const int32_t* list, const int32_t* count) {
+  if (nmats <= 0) return hipSuccess;
+  if (nmax <= 64) return eig_launch<64>(nmats, in, sr, mu, F, ev, ev_ld, st, list, count);
+  if (nmax <= 128) return eig_launch<128>(nmats, in, sr, mu, F, ev, ev_ld, st, list, count);
+  if (nmax <= 256) return eig_launch<256>(nmats, in, sr, mu, F, ev, ev_ld, st, list, count);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace tca

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
@@ -102,6 +103,18 @@ struct tca_ctx {
   std::vector<hipEvent_t> prof;  // event pool for TCA_FLAG_PROFILE
   tca_surrogate* sg = nullptr;   // first stage of delayed acceptance, or none
   tca::DaBufs da;
+  bool own_stream = false;       // stream created by the context (none was given)
+  // device-side sweep schedule of the current call: sweep counter base, index
+  // of the sweep being run, temperatures
+  uint64_t* sched_base = nullptr;
+  int32_t* sched_idx = nullptr;
+  double* sched_T = nullptr;
+  int sched_cap = 0;
+  uint64_t sched_host_base = 0;
+  hipGraphExec_t graph_exec = nullptr;  // one captured sweep, replayed per sweep
+  uintptr_t graph_key[4] = {0, 0, 0, 0};
+  int64_t graph_captures = 0;
+  std::string tune_report;
 };
 
 namespace tca {
@@ -111,4 +124,7 @@ int run_sweeps(tca_ctx* c, const double* T, int32_t nsweeps, tca_update_record* 
                tca_sweep_stats* st, tca_surrogate* collect, int64_t row0);
 // TCA_E_INVAL unless T holds nsweeps finite positive temperatures.
 int check_temps(const double* T, int32_t nsweeps);
+// Changes whenever the autotuner records a new reducer choice (captured
+// graphs depending on the old choice are then re-captured).
+int tuning_generation();
 }  // namespace tca

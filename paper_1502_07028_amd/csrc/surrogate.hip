@@ -445,17 +445,20 @@ hipError_t sg_f32_to_bf16_rows(const float* X, int rows, int n_in, int kpad, uin
 // proposal, T) and of the reverse move (corner = proposal, proposing the old spin).
 template <bool COLLECT>
 __global__ __launch_bounds__(64) void sg_features_kernel(const double* __restrict__ S,
-                                                         BlockGeom g, int Lc, ModelParams m,
-                                                         uint64_t sweep, double T,
-                                                         SurrogateDims dm, uint16_t* Fin,
-                                                         const double* F, float* X, float* y) {
+                                                         BlockGeom g, int K, int Lc, ModelParams m,
+                                                         SweepRef sr, SurrogateDims dm,
+                                                         uint16_t* Fin, const double* F, float* X,
+                                                         float* y, int64_t row0) {
   __shared__ double prop[3];
   const int c = blockIdx.x;
   const int px = g.x0 + c % g.h, py = g.y0 + c / g.h;
-  if (threadIdx.x == 0) sphere_point(m.seed, sweep, (uint64_t)(px + g.L * py), kStreamProposal, prop);
+  const double T = sr.T();
+  if (threadIdx.x == 0)
+    sphere_point(m.seed, sr.sweep(), (uint64_t)(px + g.L * py), kStreamProposal, prop);
   __syncthreads();
   const int Nc = Lc * Lc;
   const int width = COLLECT ? dm.n_in : dm.kpad;
+  const int64_t row = row0 + ((int64_t)sr.s() * 4 + K) * (int64_t)(g.h * g.h) + c;
   for (int k = threadIdx.x; k < width; k += 64) {
     double vf = 0.0, vr = 0.0;
     if (k < 3 * Nc) {
@@ -471,37 +474,39 @@ __global__ __launch_bounds__(64) void sg_features_kernel(const double* __restric
       vf = vr = T / kSurrogateTRef;
     }
     if (COLLECT) {
-      X[(size_t)c * dm.n_in + k] = (float)vf;
+      X[row * dm.n_in + k] = (float)vf;
     } else {
       Fin[(size_t)(2 * c) * dm.kpad + k] = f2bf((float)vf);
       Fin[(size_t)(2 * c + 1) * dm.kpad + k] = f2bf((float)vr);
     }
   }
-  if (COLLECT && threadIdx.x == 0) y[c] = (float)(F[2 * c + 1] - F[2 * c]);
+  if (COLLECT && threadIdx.x == 0) y[row] = (float)(F[2 * c + 1] - F[2 * c]);
 }
 
-hipError_t sg_block_features(const double* S, BlockGeom g, int Lc, ModelParams m, uint64_t sweep,
-                             double T, const SurrogateDims& dm, uint16_t* Fin, hipStream_t st) {
-  hipLaunchKernelGGL(sg_features_kernel<false>, dim3(g.h * g.h), dim3(64), 0, st, S, g, Lc, m,
-                     sweep, T, dm, Fin, (const double*)nullptr, (float*)nullptr, (float*)nullptr);
+hipError_t sg_block_features(const double* S, BlockGeom g, int Lc, ModelParams m, SweepRef sr,
+                             const SurrogateDims& dm, uint16_t* Fin, hipStream_t st) {
+  hipLaunchKernelGGL(sg_features_kernel<false>, dim3(g.h * g.h), dim3(64), 0, st, S, g, 0, Lc, m,
+                     sr, dm, Fin, (const double*)nullptr, (float*)nullptr, (float*)nullptr,
+                     (int64_t)0);
   return hipGetLastError();
 }
 
-hipError_t sg_block_collect(const double* S, BlockGeom g, int Lc, ModelParams m, uint64_t sweep,
-                            double T, const SurrogateDims& dm, const double* F, float* X, float* y,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(sg_features_kernel<true>, dim3(g.h * g.h), dim3(64), 0, st, S, g, Lc, m,
-                     sweep, T, dm, (uint16_t*)nullptr, F, X, y);
+hipError_t sg_block_collect(const double* S, BlockGeom g, int K, int Lc, ModelParams m,
+                            SweepRef sr, const SurrogateDims& dm, const double* F, float* X,
+                            float* y, int64_t row0, hipStream_t st) {
+  hipLaunchKernelGGL(sg_features_kernel<true>, dim3(g.h * g.h), dim3(64), 0, st, S, g, K, Lc, m,
+                     sr, dm, (uint16_t*)nullptr, F, X, y, row0);
   return hipGetLastError();
 }
 
-// Stage 1: pass iff ln u1 < min(0, -dS_f/T) (u1 = word 1 of the Metropolis block).
-__global__ void sg_stage1_kernel(const float* dS, BlockGeom g, ModelParams m, uint64_t sweep,
-                                 double T, uint8_t* pass, int32_t* count, int32_t* list) {
+// Stage 1: pass iff u1 == 0 or ln u1 < min(0, -dS_f/T) (u1 = word 1 of the Metropolis block).
+__global__ void sg_stage1_kernel(const float* dS, BlockGeom g, ModelParams m, SweepRef sr,
+                                 uint8_t* pass, int32_t* count, int32_t* list) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.h * g.h) return;
+  const double T = sr.T();
   const int site = (g.x0 + c % g.h) + g.L * (g.y0 + c / g.h);
-  const U64x4 r = philox4x64_10(m.seed, 0, sweep, (uint64_t)site, kStreamMetropolis, 0);
+  const U64x4 r = philox4x64_10(m.seed, 0, sr.sweep(), (uint64_t)site, kStreamMetropolis, 0);
   const double u1 = u53(r.w1);
   const double rhs = fmin(0.0, -(double)dS[2 * c] / T);
   const bool p = (u1 <= 0.0) || (log(u1) < rhs);
@@ -511,12 +516,12 @@ __global__ void sg_stage1_kernel(const float* dS, BlockGeom g, ModelParams m, ui
 
 __global__ void zero_i32_one(int32_t* p) { *p = 0; }
 
-hipError_t sg_stage1(const float* dS, BlockGeom g, ModelParams m, uint64_t sweep, double T,
-                     uint8_t* pass, int32_t* count, int32_t* list, hipStream_t st) {
+hipError_t sg_stage1(const float* dS, BlockGeom g, ModelParams m, SweepRef sr, uint8_t* pass,
+                     int32_t* count, int32_t* list, hipStream_t st) {
   hipLaunchKernelGGL(zero_i32_one, dim3(1), dim3(1), 0, st, count);
   const int hh = g.h * g.h;
-  hipLaunchKernelGGL(sg_stage1_kernel, grid1(hh), dim3(256), 0, st, dS, g, m, sweep, T, pass,
-                     count, list);
+  hipLaunchKernelGGL(sg_stage1_kernel, grid1(hh), dim3(256), 0, st, dS, g, m, sr, pass, count,
+                     list);
   return hipGetLastError();
 }
 

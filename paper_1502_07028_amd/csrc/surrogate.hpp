@@ -61,14 +61,15 @@ hipError_t sg_f32_to_bf16_rows(const float* X, int rows, int n_in, int kpad, uin
 // ---- sweep-side launches
 // BF16 feature rows 2c (forward move) and 2c+1 (reverse move) of every cluster
 // of a block, from the block-start spins
-hipError_t sg_block_features(const double* S, BlockGeom g, int Lc, ModelParams m, uint64_t sweep,
-                             double T, const SurrogateDims& dm, uint16_t* Fin, hipStream_t st);
-// dataset rows (FP32 forward-move features, target dF = F[2c+1] - F[2c]) of a block
-hipError_t sg_block_collect(const double* S, BlockGeom g, int Lc, ModelParams m, uint64_t sweep,
-                            double T, const SurrogateDims& dm, const double* F, float* X, float* y,
-                            hipStream_t st);
+hipError_t sg_block_features(const double* S, BlockGeom g, int Lc, ModelParams m, SweepRef sr,
+                             const SurrogateDims& dm, uint16_t* Fin, hipStream_t st);
+// dataset rows (FP32 forward-move features, target dF = F[2c+1] - F[2c]) of block K:
+// row row0 + (s*4 + K)*h*h + c, s the sweep index inside the call
+hipError_t sg_block_collect(const double* S, BlockGeom g, int K, int Lc, ModelParams m,
+                            SweepRef sr, const SurrogateDims& dm, const double* F, float* X,
+                            float* y, int64_t row0, hipStream_t st);
 // stage 1 of delayed acceptance: pass flags and the compacted list of passing clusters
-hipError_t sg_stage1(const float* dS, BlockGeom g, ModelParams m, uint64_t sweep, double T,
-                     uint8_t* pass, int32_t* count, int32_t* list, hipStream_t st);
+hipError_t sg_stage1(const float* dS, BlockGeom g, ModelParams m, SweepRef sr, uint8_t* pass,
+                     int32_t* count, int32_t* list, hipStream_t st);
 
 }  // namespace tca

@@ -50,14 +50,18 @@ __device__ __attribute__((noinline)) double classical_delta(const double* S, int
 // (Christen & Fox), dS_f/dS_r the surrogate on the move and its reverse.
 __global__ __launch_bounds__(1024) void decide_kernel(double* S,
                                                       const double* __restrict__ Fpair,
-                                                      BlockGeom g, ModelParams m, uint64_t sweep,
-                                                      double T, int Lc_fixed, int4 classes,
+                                                      BlockGeom g, ModelParams m, SweepRef sr,
+                                                      int Lc_fixed, int4 classes,
                                                       int n_classes, int K,
                                                       const uint8_t* __restrict__ pass,
                                                       const float* __restrict__ dS,
-                                                      tca_update_record* __restrict__ logbuf,
+                                                      tca_update_record* __restrict__ log_base,
                                                       unsigned long long* __restrict__ counters) {
   const int h = g.h, L = g.L;
+  const uint64_t sweep = sr.sweep();
+  const double T = sr.T();
+  tca_update_record* logbuf =
+      log_base != nullptr ? log_base + (size_t)sr.s() * (size_t)L * (size_t)L : nullptr;
   const bool wave = (m.JAF != 0.0);
   const int ndiag = wave ? 2 * h - 1 : 1;
   unsigned long long nacc = 0, nnear = 0, npass = 0;
@@ -141,9 +145,10 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S,
 }
 
 __global__ void classify_kernel(int4 classes, int n_classes, BlockGeom g, uint64_t seed,
-                                uint64_t sweep, int32_t* __restrict__ count,
+                                SweepRef sr, int32_t* __restrict__ count,
                                 int32_t* __restrict__ list) {
   const int hh = g.h * g.h;
+  const uint64_t sweep = sr.sweep();
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= hh) return;
   const int site = (g.x0 + c % g.h) + g.L * (g.y0 + c / g.h);
@@ -230,23 +235,29 @@ static int4 pack_classes(const int32_t* c, int n) {
 }
 
 hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g, uint64_t seed,
-                           uint64_t sweep, ClassLists cl, hipStream_t st) {
+                           SweepRef sr, ClassLists cl, hipStream_t st) {
   const int hh = g.h * g.h;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cl.count, 4);
   hipLaunchKernelGGL(classify_kernel, dim3((hh + 255) / 256), dim3(256), 0, st,
-                     pack_classes(classes_Lc, n_classes), n_classes, g, seed, sweep, cl.count,
+                     pack_classes(classes_Lc, n_classes), n_classes, g, seed, sr, cl.count,
                      cl.list);
   return hipGetLastError();
 }
 
-hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m,
-                         uint64_t sweep, double T, int Lc_fixed, const int32_t* classes_Lc,
-                         int n_classes, int K, const uint8_t* pass, const float* dS,
-                         tca_update_record* log_dev, unsigned long long* counters,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, Fpair, g, m, sweep, T,
-                     Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, K, pass, dS,
-                     log_dev, counters);
+hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m, SweepRef sr,
+                         int Lc_fixed, const int32_t* classes_Lc, int n_classes, int K,
+                         const uint8_t* pass, const float* dS, tca_update_record* log_base,
+                         unsigned long long* counters, hipStream_t st) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, Fpair, g, m, sr, Lc_fixed,
+                     pack_classes(classes_Lc, n_classes), n_classes, K, pass, dS, log_base,
+                     counters);
+  return hipGetLastError();
+}
+
+__global__ void advance_kernel(int32_t* idx) { *idx += 1; }
+
+hipError_t launch_advance(int32_t* idx, hipStream_t st) {
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(1), 0, st, idx);
   return hipGetLastError();
 }
 
@@ -260,6 +271,11 @@ hipError_t launch_sq(const double* S, int L, double* work, double* Sq, hipStream
   const int N = L * L;
   hipLaunchKernelGGL(sq_rows_kernel, dim3((N + 255) / 256), dim3(256), 0, st, S, L, work);
   hipLaunchKernelGGL(sq_cols_kernel, dim3((N + 255) / 256), dim3(256), 0, st, work, L, Sq);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 
