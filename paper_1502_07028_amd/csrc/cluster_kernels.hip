@@ -138,11 +138,13 @@ __global__ __launch_bounds__(Red::NT, Red::MINW) void heevals_reduce(const doubl
   if (threadIdx.x == 0) out.nmat[b] = n;
 }
 
-// One workgroup per tridiagonal (persistent over the matrices): thread j
-// finds eigenvalues j, j + NTHR, ...; then the grand potential is reduced in
-// a fixed order.  Every lane of a wavefront walks the same (d, e2) with the
-// same index, so the Sturm loops read them through the scalar cache straight
-// from global memory (read-only in this kernel) as scalar operands.
+// One workgroup per tridiagonal (persistent over the matrices).  The matrix is
+// staged in LDS as (d_i, e2_{i-1}) pairs.  A first pass slices the spectrum:
+// thread t counts the eigenvalues below the t-th of NTHR evenly spaced points
+// of the Gershgorin interval, which brackets every eigenvalue to one slice;
+// then thread j finishes eigenvalues j, j + NTHR, ... from their slices
+// (bisection until isolated, then safeguarded Newton), and the grand
+// potential is reduced in a fixed order.
 template <int NTHR>
 __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restrict__ D,
                                                            const double* __restrict__ E2, int ld,
@@ -152,8 +154,11 @@ __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restr
                                                            double* __restrict__ ev, int ev_ld,
                                                            const int32_t* __restrict__ list,
                                                            const int32_t* __restrict__ count) {
-  __shared__ double red[NTHR / 64];
-  const int tid = threadIdx.x;
+  constexpr int NW = NTHR / 64;
+  __shared__ double2 de[kMaxN];
+  __shared__ int cnt[NTHR];
+  __shared__ double red[NW], wlo[NW], whi[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double T = sr.T();
   const int limit = list != nullptr ? 2 * *count : nmats;
   for (int w = blockIdx.x; w < limit; w += gridDim.x) {
@@ -161,24 +166,78 @@ __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restr
     const int n = nmat[mat];
     const double* d = D + (size_t)mat * ld;
     const double* e2 = E2 + (size_t)mat * ld;
-    const TriBounds B = tri_bounds(n, d, e2);
+    // stage the pairs and the Gershgorin bounds
+    double lo = DBL_MAX, hi = -DBL_MAX;
+    for (int i = tid; i < n; i += NTHR) {
+      const double el = i > 0 ? e2[i - 1] : 0.0, er = i < n - 1 ? e2[i] : 0.0;
+      const double di = d[i];
+      de[i] = make_double2(di, el);
+      const double r = sqrt(el) + sqrt(er);
+      lo = fmin(lo, di - r);
+      hi = fmax(hi, di + r);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) {
+      wlo[wave] = lo;
+      whi[wave] = hi;
+    }
+    __syncthreads();
+    lo = wlo[0];
+    hi = whi[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+      lo = fmin(lo, wlo[q]);
+      hi = fmax(hi, whi[q]);
+    }
+    const double span = fmax(fmax(fabs(lo), fabs(hi)), DBL_MIN);
+    const double widen = 2.0 * DBL_EPSILON * span * (double)n;
+    lo -= widen;
+    hi += widen;
+    const double tol = 2.0 * DBL_EPSILON * span;
+    // slice the spectrum at x_t = lo + (t + 1) (hi - lo) / (NTHR + 1)
+    const double h = (hi - lo) / (double)(NTHR + 1);
+    cnt[tid] = sturm_count_pairs(n, fma((double)(tid + 1), h, lo), de);
+    __syncthreads();
     double acc = 0.0;
     for (int j = tid; j < n; j += NTHR) {
-      const double lam = tri_eigenvalue(n, j, d, e2, B);
+      // last slice point with count <= j (counts are nondecreasing in x)
+      int lo_t = -1, hi_t = NTHR;  // cnt[lo_t] <= j < cnt[hi_t] (virtual ends 0 and n)
+      while (hi_t - lo_t > 1) {
+        const int mid = (lo_t + hi_t) >> 1;
+        if (cnt[mid] <= j)
+          lo_t = mid;
+        else
+          hi_t = mid;
+      }
+      double a = lo_t < 0 ? lo : fma((double)(lo_t + 1), h, lo);
+      double b = hi_t >= NTHR ? hi : fma((double)(hi_t + 1), h, lo);
+      int ca = lo_t < 0 ? 0 : cnt[lo_t];
+      int cb = hi_t >= NTHR ? n : cnt[hi_t];
+      if (!(ca <= j && j < cb)) {  // a count that broke monotonicity: full interval
+        a = lo;
+        b = hi;
+        ca = 0;
+        cb = n;
+      }
+      const double lam = tri_eigenvalue_pairs(n, j, de, a, b, ca, cb, tol);
       if (ev != nullptr) ev[(size_t)mat * ev_ld + j] = lam;
       if (F != nullptr) acc += omega_term(lam, T, mu);
     }
     if (F != nullptr) {
       acc = wave_total(acc);
-      if ((tid & 63) == 0) red[tid >> 6] = acc;
+      if (lane == 0) red[wave] = acc;
       __syncthreads();
       if (tid == 0) {
         double s = 0.0;
-        for (int q = 0; q < NTHR / 64; ++q) s += red[q];
+        for (int q = 0; q < NW; ++q) s += red[q];
         F[mat] = s;
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 

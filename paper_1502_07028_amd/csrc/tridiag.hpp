@@ -193,6 +193,130 @@ __device__ inline double tri_eigenvalue(const int n, const int j, const double* 
   return 0.5 * (a + b);
 }
 
+// ---------------------------------------------------------------------------
+// The same recurrences with the matrix staged in LDS as pairs
+// de[i] = (d_i, e2_{i-1}) (e2_{-1} = 0): every lane reads the same pair, a
+// broadcast LDS read that the compiler issues ahead of the dependent chain.
+__device__ __forceinline__ int sturm_count_pairs(const int n, const double x,
+                                                 const double2* de) {
+  double pm = 1.0, p = de[0].x - x;
+  unsigned c = sign_change(p, pm);
+  int i = 1;
+  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
+    double2 q[kSturmGroup];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) q[u] = de[i + u];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+      const double pn = fma(q[u].x - x, p, -q[u].y * pm);
+      c += sign_change(pn, p);
+      pm = p;
+      p = pn;
+    }
+    const double f = rescale_factor(fmax(fabs(p), fabs(pm)));
+    p *= f;
+    pm *= f;
+  }
+  for (; i < n; ++i) {
+    const double2 q = de[i];
+    const double pn = fma(q.x - x, p, -q.y * pm);
+    c += sign_change(pn, p);
+    pm = p;
+    p = pn;
+  }
+  return (int)c;
+}
+
+__device__ __forceinline__ int sturm_newton_pairs(const int n, const double x, const double2* de,
+                                                  double* step) {
+  double pm = 1.0, p = de[0].x - x;
+  double qm = 0.0, q = -1.0;
+  unsigned c = sign_change(p, pm);
+  int i = 1;
+  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
+    double2 r[kSturmGroup];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) r[u] = de[i + u];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+      const double dx = r[u].x - x, e = r[u].y;
+      const double pn = fma(dx, p, -e * pm);
+      const double qn = fma(dx, q, -fma(e, qm, p));
+      c += sign_change(pn, p);
+      pm = p;
+      p = pn;
+      qm = q;
+      q = qn;
+    }
+    const double f = rescale_factor(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))));
+    p *= f;
+    pm *= f;
+    q *= f;
+    qm *= f;
+  }
+  for (; i < n; ++i) {
+    const double dx = de[i].x - x, e = de[i].y;
+    const double pn = fma(dx, p, -e * pm);
+    const double qn = fma(dx, q, -fma(e, qm, p));
+    c += sign_change(pn, p);
+    pm = p;
+    p = pn;
+    qm = q;
+    q = qn;
+  }
+  *step = p / q;
+  return (int)c;
+}
+
+// Eigenvalue j of T from a bracket [a, b] with counts ca <= j < cb.
+__device__ inline double tri_eigenvalue_pairs(const int n, const int j, const double2* de,
+                                              double a, double b, int ca, int cb,
+                                              const double tol) {
+  int extra = 2;
+  while (b - a > tol) {
+    if (ca == j && cb == j + 1 && extra-- <= 0) break;
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    const int c = sturm_count_pairs(n, mid, de);
+    if (c > j) {
+      b = mid;
+      cb = c;
+    } else {
+      a = mid;
+      ca = c;
+    }
+  }
+  if (b - a <= tol) return 0.5 * (a + b);
+  double x = 0.5 * (a + b);
+  double last = b - a;
+  for (int it = 0; it < 12; ++it) {
+    double step;
+    const int c = sturm_newton_pairs(n, x, de, &step);
+    if (c > j)
+      b = x;
+    else
+      a = x;
+    if (b - a <= tol) return 0.5 * (a + b);
+    double xn = x - step;
+    const bool inside = xn > a && xn < b;
+    const double st = fabs(step);
+    if (st <= tol) return xn;
+    if (st <= 1e5 * tol && (st > 0.5 * last || !inside)) return x;
+    if (!inside) xn = 0.5 * (a + b);
+    last = inside ? st : b - a;
+    x = xn;
+  }
+  while (b - a > tol) {
+    const double mid = 0.5 * (a + b);
+    if (mid <= a || mid >= b) break;
+    if (sturm_count_pairs(n, mid, de) > j)
+      b = mid;
+    else
+      a = mid;
+  }
+  return 0.5 * (a + b);
+}
+
 // Grand potential term of one level: min(x,0) - T log1p(exp(-|x|/T)), x = eps - mu.
 __device__ __forceinline__ double omega_term(const double eps, const double T, const double mu) {
   const double x = eps - mu;
