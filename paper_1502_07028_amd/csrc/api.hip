@@ -77,6 +77,7 @@ static void free_ctx(tca_ctx* c) {
   if (c->cls_count) (void)hipFree(c->cls_count);
   if (c->cls_list) (void)hipFree(c->cls_list);
   if (c->counters) (void)hipFree(c->counters);
+  if (c->prep) (void)hipFree(c->prep);
   if (c->sq_work) (void)hipFree(c->sq_work);
   if (c->sq_out) (void)hipFree(c->sq_out);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -254,6 +255,7 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
   if (e == hipSuccess) e = hipMalloc((void**)&c->cls_count, sizeof(int32_t) * 4);
   if (e == hipSuccess) e = hipMalloc((void**)&c->cls_list, sizeof(int32_t) * 4 * hh);
   if (e == hipSuccess) e = hipMalloc((void**)&c->counters, sizeof(unsigned long long) * 4);
+  if (e == hipSuccess) e = hipMalloc(&c->prep, decide_prep_bytes((int)hh));
   if (e == hipSuccess) e = hipMalloc((void**)&c->sched_base, sizeof(uint64_t));
   if (e == hipSuccess) e = hipMalloc((void**)&c->sched_idx, sizeof(int32_t));
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
@@ -367,8 +369,8 @@ static int issue_sweep(tca_ctx* c, SweepRef sr, int32_t* idx, tca_update_record*
                               collect->y.p, row0, c->stream));
     TCA_CK(pr.begin());
     TCA_CK(launch_decide(c->S, c->F, g, m, sr, c->p.Lc, c->p.Lc_classes, c->p.n_classes, K,
-                         sg ? c->da.pass.p : nullptr, sg ? c->da.dS.p : nullptr, dlog, c->counters,
-                         c->stream));
+                         sg ? c->da.pass.p : nullptr, sg ? c->da.dS.p : nullptr, c->prep, dlog,
+                         c->counters, c->stream));
     TCA_CK(pr.end(2));
   }
   TCA_CK(launch_advance(idx, c->stream));

@@ -96,6 +96,7 @@ struct tca_ctx {
   int32_t* cls_count = nullptr;  // 4
   int32_t* cls_list = nullptr;   // 4 * h*h
   unsigned long long* counters = nullptr;  // 4: accepted, near-threshold, updates, stage-1 passes
+  void* prep = nullptr;          // per-cluster decision records of one block
   double* sq_work = nullptr;     // 6 N
   double* sq_out = nullptr;      // N
   uint64_t sweep_counter = 0;

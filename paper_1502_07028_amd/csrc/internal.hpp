@@ -96,11 +96,14 @@ hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g
                            SweepRef sr, ClassLists cl, hipStream_t st);
 
 // pass/dS: stage-1 flags and surrogate values of delayed acceptance, or nullptr
-// log_base: records of the whole call (sweep s of the call at log_base + s*L*L), or nullptr
+// log_base: records of the whole call (sweep s of the call at log_base + s*L*L), or nullptr;
+// prep: decide_prep_bytes(h*h) bytes of device scratch
 hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m, SweepRef sr,
                          int Lc_fixed, const int32_t* classes_Lc, int n_classes, int K,
-                         const uint8_t* pass, const float* dS, tca_update_record* log_base,
-                         unsigned long long* counters, hipStream_t st);
+                         const uint8_t* pass, const float* dS, void* prep,
+                         tca_update_record* log_base, unsigned long long* counters,
+                         hipStream_t st);
+size_t decide_prep_bytes(int clusters);
 
 // *idx += 1 (end of a sweep inside a call)
 hipError_t launch_advance(int32_t* idx, hipStream_t st);

@@ -35,30 +35,91 @@ __device__ __attribute__((noinline)) double classical_delta(const double* S, int
   return JAF * dot;
 }
 
-// Metropolis decisions of block K.  Each cluster's dF came from the
-// block-start state, which equals the state the sequential sweep would have
-// shown it (no cluster of a block contains a site visited earlier in that
-// block).  The classical term reads the -x and -y lattice neighbours, which
-// may belong to the same block and be decided earlier in raster order, so with
-// J_AF != 0 the sites are processed by anti-diagonals i + j = const of the
-// block: every site is decided after both of those neighbours, exactly as in
-// the sequential order.  With J_AF == 0 all decisions are independent.
+// Metropolis decisions of block K, in two kernels.
+//
+// decide_prep_kernel (one thread per cluster, fully parallel): everything of
+// an update that does not depend on earlier decisions of the block -- the
+// Metropolis uniforms, the proposal, dF = F_new - F_old, ln u and the
+// surrogate terms -- into one record per cluster.
+//
+// decide_kernel (one workgroup): the decisions themselves.  Each cluster's dF
+// came from the block-start state, which equals the state the sequential
+// sweep would have shown it (no cluster of a block contains a site visited
+// earlier in that block).  The classical term reads the -x and -y lattice
+// neighbours, which may belong to the same block and be decided earlier in
+// raster order, so with J_AF != 0 the sites are processed by anti-diagonals
+// i + j = const of the block: every site is decided after both of those
+// neighbours, exactly as in the sequential order.  With J_AF == 0 all
+// decisions are independent.
 //
 // With delayed acceptance (pass != nullptr) only clusters that passed the
 // surrogate stage were solved exactly; the others are rejected, and a passing
 // one is accepted iff ln u < -dE/T + min(0, -dS_r/T) - min(0, -dS_f/T)
 // (Christen & Fox), dS_f/dS_r the surrogate on the move and its reverse.
-__global__ __launch_bounds__(1024) void decide_kernel(double* S,
-                                                      const double* __restrict__ Fpair,
-                                                      BlockGeom g, ModelParams m, SweepRef sr,
-                                                      int Lc_fixed, int4 classes,
-                                                      int n_classes, int K,
-                                                      const uint8_t* __restrict__ pass,
-                                                      const float* __restrict__ dS,
+struct DecidePrep {
+  double sn[3];     // proposal
+  double dF;        // F_new - F_old (NaN when stage 1 rejected)
+  double u, lnu;    // Metropolis uniform and its logarithm (lnu unused when u == 0)
+  double sa, sb;    // min(0, -dS_r/T), min(0, -dS_f/T)
+  float dSf, dSr;
+  int16_t Lc;
+  uint8_t flags;    // bit 1: reached the exact stage; bit 2: stage 1 near threshold
+  uint8_t pad[5];
+};
+
+__global__ __launch_bounds__(256) void decide_prep_kernel(const double* __restrict__ Fpair,
+                                                          BlockGeom g, ModelParams m, SweepRef sr,
+                                                          int Lc_fixed, int4 classes,
+                                                          int n_classes,
+                                                          const uint8_t* __restrict__ pass,
+                                                          const float* __restrict__ dS,
+                                                          DecidePrep* __restrict__ prep) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.h * g.h) return;
+  const uint64_t sweep = sr.sweep();
+  const double T = sr.T();
+  const int site = (g.x0 + c % g.h) + g.L * (g.y0 + c / g.h);
+  const U64x4 r = philox4x64_10(m.seed, 0, sweep, site, kStreamMetropolis, 0);
+  DecidePrep q;
+  q.u = u53(r.w0);
+  q.lnu = q.u > 0.0 ? log(q.u) : 0.0;
+  const bool stage1 = (pass == nullptr) || (pass[c] != 0);
+  bool near1 = false;
+  q.dSf = q.dSr = 0.0f;
+  q.sa = q.sb = 0.0;
+  if (pass != nullptr) {
+    q.dSf = dS[2 * c];
+    q.dSr = dS[2 * c + 1];
+    q.sa = fmin(0.0, -(double)q.dSr / T);
+    q.sb = fmin(0.0, -(double)q.dSf / T);
+    const double u1 = u53(r.w1);
+    if (u1 > 0.0)
+      near1 = fabs(T * (log(u1) - fmin(0.0, -(double)q.dSf / T))) <=
+              1e-9 * fmax(fabs((double)q.dSf), 1e-3);
+  }
+  q.dF = __builtin_nan("");
+  q.sn[0] = q.sn[1] = 0.0;
+  q.sn[2] = 1.0;
+  if (stage1) {
+    sphere_point(m.seed, sweep, site, kStreamProposal, q.sn);
+    q.dF = Fpair[2 * c + 1] - Fpair[2 * c];
+  }
+  int Lc = Lc_fixed;
+  if (n_classes > 0) {
+    const int k = size_class(m.seed, sweep, site, n_classes);
+    Lc = k == 0 ? classes.x : k == 1 ? classes.y : k == 2 ? classes.z : classes.w;
+  }
+  q.Lc = (int16_t)Lc;
+  q.flags = (uint8_t)((stage1 ? 2 : 0) | (near1 ? 4 : 0));
+  prep[c] = q;
+}
+
+__global__ __launch_bounds__(1024) void decide_kernel(double* S, BlockGeom g, ModelParams m,
+                                                      SweepRef sr, int K, bool da,
+                                                      const DecidePrep* __restrict__ prep,
                                                       tca_update_record* __restrict__ log_base,
                                                       unsigned long long* __restrict__ counters) {
   const int h = g.h, L = g.L;
-  const uint64_t sweep = sr.sweep();
   const double T = sr.T();
   tca_update_record* logbuf =
       log_base != nullptr ? log_base + (size_t)sr.s() * (size_t)L * (size_t)L : nullptr;
@@ -79,60 +140,40 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S,
       }
       const int c = i + h * j;
       const int px = g.x0 + i, py = g.y0 + j, site = px + L * py;
-      const U64x4 r = philox4x64_10(m.seed, 0, sweep, site, kStreamMetropolis, 0);
-      const double u = u53(r.w0);
-      const bool stage1 = (pass == nullptr) || (pass[c] != 0);
-      float dSf = 0.0f, dSr = 0.0f;
-      bool near1 = false;
-      if (pass != nullptr) {
-        dSf = dS[2 * c];
-        dSr = dS[2 * c + 1];
-        const double u1 = u53(r.w1);
-        if (u1 > 0.0)
-          near1 = fabs(T * (log(u1) - fmin(0.0, -(double)dSf / T))) <=
-                  1e-9 * fmax(fabs((double)dSf), 1e-3);
-      }
-      double dF = __builtin_nan(""), dE = __builtin_nan("");
+      const DecidePrep pr = prep[c];
+      const bool stage1 = (pr.flags & 2) != 0;
+      double dE = __builtin_nan("");
       bool acc = false, near = false;
       if (stage1) {
-        double sn[3];
-        sphere_point(m.seed, sweep, site, kStreamProposal, sn);
-        dF = Fpair[2 * c + 1] - Fpair[2 * c];
-        dE = dF + classical_delta(S, L, px, py, sn, m.JAF);
-        if (pass == nullptr) {
-          acc = (dE <= 0.0) || (u < exp(-dE / T));
-          if (u > 0.0) near = fabs(dE + T * log(u)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+        dE = pr.dF + classical_delta(S, L, px, py, pr.sn, m.JAF);
+        if (!da) {
+          acc = (dE <= 0.0) || (pr.u < exp(-dE / T));
+          if (pr.u > 0.0) near = fabs(dE + T * pr.lnu) <= 1e-9 * fmax(fabs(dE), 1e-3);
         } else {
-          const double rhs =
-              -dE / T + fmin(0.0, -(double)dSr / T) - fmin(0.0, -(double)dSf / T);
-          acc = (u <= 0.0) || (log(u) < rhs);
-          if (u > 0.0) near = fabs(T * (log(u) - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+          const double rhs = -dE / T + pr.sa - pr.sb;
+          acc = (pr.u <= 0.0) || (pr.lnu < rhs);
+          if (pr.u > 0.0) near = fabs(T * (pr.lnu - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
         }
         if (acc) {
-          S[3 * site + 0] = sn[0];
-          S[3 * site + 1] = sn[1];
-          S[3 * site + 2] = sn[2];
+          S[3 * site + 0] = pr.sn[0];
+          S[3 * site + 1] = pr.sn[1];
+          S[3 * site + 2] = pr.sn[2];
         }
       }
       nacc += acc;
       nnear += near;
       npass += stage1;
       if (logbuf != nullptr) {
-        int Lc = Lc_fixed;
-        if (n_classes > 0) {
-          const int k = size_class(m.seed, sweep, site, n_classes);
-          Lc = k == 0 ? classes.x : k == 1 ? classes.y : k == 2 ? classes.z : classes.w;
-        }
         tca_update_record rec;
         rec.site = site;
-        rec.Lc = (int16_t)Lc;
+        rec.Lc = pr.Lc;
         rec.accept = acc ? 1 : 0;
-        rec.flags = (uint8_t)((near ? 1 : 0) | (stage1 ? 2 : 0) | (near1 ? 4 : 0));
-        rec.dF = dF;
+        rec.flags = (uint8_t)((near ? 1 : 0) | pr.flags);
+        rec.dF = pr.dF;
         rec.dE = dE;
-        rec.u = u;
-        rec.dS_f = dSf;
-        rec.dS_r = dSr;
+        rec.u = pr.u;
+        rec.dS_f = pr.dSf;
+        rec.dS_r = pr.dSr;
         logbuf[(size_t)K * h * h + c] = rec;
       }
     }
@@ -246,13 +287,19 @@ hipError_t launch_classify(const int32_t* classes_Lc, int n_classes, BlockGeom g
 
 hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParams m, SweepRef sr,
                          int Lc_fixed, const int32_t* classes_Lc, int n_classes, int K,
-                         const uint8_t* pass, const float* dS, tca_update_record* log_base,
-                         unsigned long long* counters, hipStream_t st) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, Fpair, g, m, sr, Lc_fixed,
-                     pack_classes(classes_Lc, n_classes), n_classes, K, pass, dS, log_base,
-                     counters);
+                         const uint8_t* pass, const float* dS, void* prep_buf,
+                         tca_update_record* log_base, unsigned long long* counters,
+                         hipStream_t st) {
+  DecidePrep* prep = (DecidePrep*)prep_buf;
+  const int hh = g.h * g.h;
+  hipLaunchKernelGGL(decide_prep_kernel, dim3((hh + 255) / 256), dim3(256), 0, st, Fpair, g, m, sr,
+                     Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, pass, dS, prep);
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, g, m, sr, K, pass != nullptr,
+                     (const DecidePrep*)prep, log_base, counters);
   return hipGetLastError();
 }
+
+size_t decide_prep_bytes(int clusters) { return sizeof(DecidePrep) * (size_t)clusters; }
 
 __global__ void advance_kernel(int32_t* idx) { *idx += 1; }
 
