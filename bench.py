@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix): 256 CU x 2.4 GHz x 128 flop/clk/CU
 PEAK_FP32_VALU_TFLOPS = 78.6   # FP32 vector without packed math, same issue rate as FP64
+# HBM bytes per launch of the FP64 fused reduction at the headline workload, from the
+# FETCH_SIZE / WRITE_SIZE counters of `bench.py --counter-run` scaled by the calibration
+# transfers (FETCH_SIZE x 1.996, WRITE_SIZE x 1.0); re-measure whenever the kernel changes.
+TRAFFIC_BYTES_FP64_REDUCE = 2.48e6
 
 
 def reduce_flops(n):
@@ -48,6 +52,10 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=8)
     ap.add_argument("--no-full-form", action="store_true")
     ap.add_argument("--full-sweeps", type=int, default=200)
+    ap.add_argument("--counter-run", action="store_true",
+                    help="for hardware-counter runs: two FP64 sweeps of the headline workload, then "
+                         "a 64 MiB fill and a 64 MiB sum whose byte counts calibrate FETCH_SIZE and "
+                         "WRITE_SIZE; prints no JSON")
     ap.add_argument("--sq-check-sweeps", type=int, default=40,
                     help="anneal length of the S(q) comparison of the two chains (0 = skip)")
     return ap.parse_args()
@@ -193,6 +201,16 @@ def main():
     n = 2 * Lc * Lc
     h = L // 2
     torch.cuda.set_device(0)
+    if a.counter_run:
+        lat = tca.Lattice(L, Lc, seed=seed, JH=8.0, JAF=JAF, flags=tca.TCA_FLAG_NO_AUTOTUNE)
+        lat.sweep([T, T])
+        lat.close()
+        x = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        x.fill_(1.0)
+        s = x.sum()
+        torch.cuda.synchronize()
+        print(f"counter run done ({float(s):.0f})", file=sys.stderr)
+        return
     stream_obj = torch.cuda.Stream()
     stream = stream_obj.cuda_stream
 
@@ -271,7 +289,8 @@ def main():
                       "decide": sp["decide_ms"] / max(1, sp["decide_launches"])},
         "autotuner": report.strip().splitlines() + report_m.strip().splitlines(),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": TRAFFIC_BYTES_FP64_REDUCE,
                      "kernel": "cluster_block_reduce<ReduceFused<32,16,4,8,double>>",
                      "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
