@@ -271,6 +271,17 @@ int tca_surrogate_eval(tca_surrogate* s, const float* X, int32_t rows, int32_t b
  * attachment. */
 int tca_attach_surrogate(tca_ctx* c, tca_surrogate* s);
 
+/* Reducer variants for matrices of dimension n (2..200) at a precision:
+ * host out count (>= 1) and, if name is not NULL, a static name of `variant`
+ * (NULL if out of range). */
+int tca_reducer_variants(int32_t n, int32_t precision, int32_t variant, int32_t* count,
+                         const char** name);
+
+/* Use `variant` for every later reduction of dimension class n at this
+ * precision in the process (overrides and disables the autotuner for that
+ * class; meant for tests and tuning studies). */
+int tca_select_reducer_variant(int32_t n, int32_t precision, int32_t variant);
+
 /* Text of the autotuner's timings and choices for this context's cluster
  * sizes (host buf of len bytes, NUL-terminated, truncated if needed). */
 int tca_tuning_report(tca_ctx* c, char* buf, int32_t len);

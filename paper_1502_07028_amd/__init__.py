@@ -89,6 +89,9 @@ _SIGS = {
     "tca_surrogate_eval": [_P, _F, ctypes.c_int32, ctypes.c_int32, _F],
     "tca_attach_surrogate": [_P, _P],
     "tca_tuning_report": [_P, ctypes.c_char_p, ctypes.c_int32],
+    "tca_reducer_variants": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _I,
+                             ctypes.POINTER(ctypes.c_char_p)],
+    "tca_select_reducer_variant": [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -173,6 +176,25 @@ def tca_tuning_report(ctx):
     buf = ctypes.create_string_buffer(4096)
     _check(_lib.tca_tuning_report(ctx, buf, len(buf)), "tca_tuning_report")
     return buf.value.decode()
+
+
+def tca_reducer_variants(n, precision=TCA_FP64):
+    """Names of the reducer variants for dimension n at a precision."""
+    cnt = ctypes.c_int32()
+    _check(_lib.tca_reducer_variants(int(n), int(precision), 0, ctypes.byref(cnt), None),
+           "tca_reducer_variants")
+    out = []
+    for v in range(cnt.value):
+        nm = ctypes.c_char_p()
+        _check(_lib.tca_reducer_variants(int(n), int(precision), v, ctypes.byref(cnt),
+                                         ctypes.byref(nm)), "tca_reducer_variants")
+        out.append(nm.value.decode())
+    return out
+
+
+def tca_select_reducer_variant(n, precision, variant):
+    _check(_lib.tca_select_reducer_variant(int(n), int(precision), int(variant)),
+           "tca_select_reducer_variant")
 
 
 def tca_destroy(ctx):

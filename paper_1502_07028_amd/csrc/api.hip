@@ -170,6 +170,34 @@ static int autotune(tca_ctx* c) {
 
 extern "C" {
 
+int tca_reducer_variants(int32_t n, int32_t precision, int32_t variant, int32_t* count,
+                         const char** name) {
+  g_err[0] = 0;
+  if (!count) TCA_INVAL("count is NULL");
+  if (!supported_n(n)) TCA_INVAL("n must satisfy 2 <= n <= 200");
+  if (precision != TCA_FP64 && precision != TCA_MIXED) TCA_INVAL("bad precision");
+  const int cls = reducer_class(n);
+  *count = reducer_variants(cls, precision);
+  if (name) *name = (variant >= 0 && variant < *count) ? reducer_name(cls, precision, variant) : nullptr;
+  return TCA_OK;
+}
+
+int tca_select_reducer_variant(int32_t n, int32_t precision, int32_t variant) {
+  g_err[0] = 0;
+  if (!supported_n(n)) TCA_INVAL("n must satisfy 2 <= n <= 200");
+  if (precision != TCA_FP64 && precision != TCA_MIXED) TCA_INVAL("bad precision");
+  const int cls = reducer_class(n);
+  if (variant < 0 || variant >= reducer_variants(cls, precision)) TCA_INVAL("variant out of range");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  set_reducer_choice(cls, precision, variant);
+  const int prec = precision == TCA_MIXED ? 1 : 0;
+  g_tuned[prec][cls] = true;
+  g_tune_log[prec][cls] = "n=" + std::to_string(n) + (prec ? " mixed" : " fp64") + ": selected " +
+                          reducer_name(cls, precision, variant);
+  g_tune_gen.fetch_add(1);
+  return TCA_OK;
+}
+
 int tca_tuning_report(tca_ctx* c, char* buf, int32_t len) {
   g_err[0] = 0;
   if (!c || !buf || len < 1) TCA_INVAL("NULL argument or len < 1");

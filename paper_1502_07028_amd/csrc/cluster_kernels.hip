@@ -73,7 +73,7 @@ template <class Red, typename R>
 __device__ __forceinline__ void solve_cluster(const double* sp, int Lc, const ModelParams& m,
                                               typename Red::Smem& sm, double* d, double* e2) {
   const int n = 2 * Lc * Lc;
-  cx<R> A[Red::NLOC];
+  typename Red::Regs A;
   Red::load(A, n, [&](int i, int j) { return h_elem<R>(i, j, Lc, m.t, m.JH, sp); });
   Red::run(n, A, sm, d, e2);
 }
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(Red::NT, Red::MINW) void heevals_reduce(const doubl
   __shared__ typename Red::Smem sm;
   const int b = blockIdx.x;
   const double* M = Ag + (size_t)b * n * n * 2;
-  cx<R> A[Red::NLOC];
+  typename Red::Regs A;
   Red::load(A, n, [&](int i, int j) -> cx<R> {
     const size_t o = 2 * ((size_t)i * n + j);
     return {(R)M[o], i == j ? R(0) : (R)M[o + 1]};
@@ -258,9 +258,11 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
       case 1: return v == 0 ? f(ReduceFused<16, 16, 4, 4, R>{}, R{}) : f(ReduceFull<16, 16, 4, 4, R>{}, R{});
       case 2: return v == 0 ? f(ReduceFused<16, 16, 5, 5, R>{}, R{}) : f(ReduceFull<16, 16, 5, 5, R>{}, R{});
       case 3:
-        return v == 0 ? f(ReduceFused<32, 16, 4, 8, R>{}, R{})
+        return v == 0   ? f(ReduceFused<32, 16, 4, 8, R>{}, R{})
                : v == 1 ? f(ReduceFused<32, 16, 4, 8, R, 2>{}, R{})
-                        : f(ReduceFull<32, 16, 4, 8, R>{}, R{});
+               : v == 2 ? f(ReduceFull<32, 16, 4, 8, R>{}, R{})
+               : v == 3 ? f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{})
+                        : f(ReduceFused<32, 16, 4, 8, R, 2, true>{}, R{});
       case 4: return v == 0 ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{}) : f(ReduceFull<32, 16, 6, 11, R>{}, R{});
       case 5: return v == 0 ? f(ReduceFused<32, 16, 7, 13, R, 2>{}, R{}) : f(ReduceFull<32, 16, 7, 13, R>{}, R{});
     }
@@ -270,7 +272,10 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
       case 0: return v == 0 ? f(ReduceFused<8, 8, 4, 4, R>{}, R{}) : f(ReduceFull<8, 8, 4, 4, R>{}, R{});
       case 1: return v == 0 ? f(ReduceFused<16, 16, 4, 4, R>{}, R{}) : f(ReduceFull<16, 16, 4, 4, R>{}, R{});
       case 2: return v == 0 ? f(ReduceFused<16, 16, 5, 5, R>{}, R{}) : f(ReduceFull<16, 16, 5, 5, R>{}, R{});
-      case 3: return v == 0 ? f(ReduceFused<32, 16, 4, 8, R>{}, R{}) : f(ReduceFull<32, 16, 4, 8, R>{}, R{});
+      case 3:
+        return v == 0   ? f(ReduceFused<32, 16, 4, 8, R>{}, R{})
+               : v == 1 ? f(ReduceFull<32, 16, 4, 8, R>{}, R{})
+                        : f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{});
       case 4: return f(ReduceLower<16, 11, R>{}, R{});
       case 5: return f(ReduceLower<16, 13, R>{}, R{});
     }
@@ -278,20 +283,22 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
   return hipErrorInvalidValue;
 }
 
-static const char* const kVariantNames[2][kNumReducerClasses][3] = {
-    {{"fused 8x8 grid", "two-pass 8x8 grid", nullptr},
-     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
-     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
-     {"fused 32x16 grid", "two-pass 32x16 grid", nullptr},
-     {"lower-triangle 16x16 grid", nullptr, nullptr},
-     {"lower-triangle 16x16 grid", nullptr, nullptr}},
-    {{"fused 8x8 grid", "two-pass 8x8 grid", nullptr},
-     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
-     {"fused 16x16 grid", "two-pass 16x16 grid", nullptr},
+constexpr int kMaxVariants = 5;
+static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
+    {{"fused 8x8 grid", "two-pass 8x8 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid"},
+     {"fused 32x16 grid", "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA"},
+     {"lower-triangle 16x16 grid"},
+     {"lower-triangle 16x16 grid"}},
+    {{"fused 8x8 grid", "two-pass 8x8 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid"},
      {"fused 32x16 grid, 2 workgroups/CU", "fused 32x16 grid, 1 workgroup/CU",
-      "two-pass 32x16 grid"},
-     {"fused 32x16 grid", "two-pass 32x16 grid", nullptr},
-     {"fused 32x16 grid", "two-pass 32x16 grid", nullptr}}};
+      "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
+      "fused 32x16 grid, rank-2 update on MFMA, 1 workgroup/CU"},
+     {"fused 32x16 grid", "two-pass 32x16 grid"},
+     {"fused 32x16 grid", "two-pass 32x16 grid"}}};
 
 static std::atomic<int> g_choice[2][kNumReducerClasses];
 
@@ -303,7 +310,7 @@ int reducer_class(int n) {
 
 int reducer_variants(int cls, int precision) {
   int v = 0;
-  while (v < 3 && kVariantNames[precision == TCA_MIXED][cls][v] != nullptr) ++v;
+  while (v < kMaxVariants && kVariantNames[precision == TCA_MIXED][cls][v] != nullptr) ++v;
   return v;
 }
 

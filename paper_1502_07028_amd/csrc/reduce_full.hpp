@@ -151,6 +151,7 @@ struct ReduceFull {
   static constexpr int NPC = TC * LC;   // padded column extent
   static constexpr int NP = NPR > NPC ? NPR : NPC;
   static constexpr int NLOC = LR * LC;
+  typedef cx<R> Regs[NLOC];
   static constexpr int NV = 2 * LR;                       // row-sum values per lane
   static constexpr int PV = pow2_ceil<NV>::value < 8 ? 8 : pow2_ceil<NV>::value;
   // minimum wavefronts per SIMD to compile for (launch bounds): four when the

@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "cplx.hpp"
 #include "reduce_full.hpp"
 
@@ -51,7 +53,26 @@ __device__ __forceinline__ float fast_rcp(float x) {
   return fmaf(r, e, r);
 }
 
-template <int TR, int TC, int LR, int LC, typename R, int MW = 0>
+template <typename R>
+struct Vec4Of;
+template <>
+struct Vec4Of<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec4Of<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+};
+
+// MF = true: the rank-2 update of each 16 x 16 tile runs on the matrix cores.
+// With the 32 x 16 grid and LR = 4, the four registers (li = 0..3) of one
+// column block lj held by the 16-lane group g of wavefront w are exactly an
+// MFMA 16 x 16 accumulator tile: rows 4w + g + 32 li, columns 16 lj + (lane
+// % 16).  The real and imaginary parts of A - v w^H - w v^H are each one
+// K = 4 product (operands: the row components of v and w, negated, times the
+// column components of w and v), i.e. two v_mfma_*_16x16x4 per tile per step;
+// the matrix-vector product stays on the vector ALUs.
+template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false>
 struct ReduceFused {
   static constexpr int NT = TR * TC;
   static constexpr int NW = NT / 64;
@@ -67,6 +88,30 @@ struct ReduceFused {
   static_assert(NT % 64 == 0 && 64 % TC == 0, "bad thread grid");
   static_assert(TR % TC == 0, "row groups must be a multiple of the column groups");
   static_assert(PV <= TC, "row group too narrow for the reduce-scatter");
+  static_assert(!MF || (TR == 32 && TC == 16 && LR == 4), "matrix-core tiles need the 32x16 grid");
+  typedef typename Vec4Of<R>::type R4;
+
+  // Register storage: per (li, lj) complex entries, or per column block one
+  // accumulator tile of real parts and one of imaginary parts.
+  struct TileRegs {
+    R4 re[LC], im[LC];
+  };
+  typedef typename std::conditional<MF, TileRegs, cx<R>[NLOC]>::type Regs;
+
+  static __device__ __forceinline__ cx<R> get(const Regs& A, int li, int lj) {
+    if constexpr (MF)
+      return {A.re[lj][li], A.im[lj][li]};
+    else
+      return A[li * LC + lj];
+  }
+  static __device__ __forceinline__ void set(Regs& A, int li, int lj, cx<R> v) {
+    if constexpr (MF) {
+      A.re[lj][li] = v.re;
+      A.im[lj][li] = v.im;
+    } else {
+      A[li * LC + lj] = v;
+    }
+  }
 
   struct Smem {
     cx<R> col[2][NP];    // column k+1 of A^{(k)} (double-buffered by column parity)
@@ -92,7 +137,7 @@ struct ReduceFused {
   }
 
   template <class F>
-  static __device__ __forceinline__ void load(cx<R> (&A)[NLOC], const int n, F&& lower) {
+  static __device__ __forceinline__ void load(Regs& A, const int n, F&& lower) {
     const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
 #pragma unroll
     for (int li = 0; li < LR; ++li) {
@@ -108,15 +153,14 @@ struct ReduceFused {
             v.im = -v.im;
           }
         }
-        A[idx(li, lj)] = v;
+        set(A, li, lj, v);
       }
     }
   }
 
   // Column `wc` of the registers -> colbuf (all owned rows; only rows >= wc
   // are read later).
-  static __device__ __forceinline__ void store_col(const cx<R> (&A)[NLOC], const int wc,
-                                                   cx<R>* colbuf) {
+  static __device__ __forceinline__ void store_col(const Regs& A, const int wc, cx<R>* colbuf) {
     const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
     if (tc != wc % TC) return;
     const int lw = wc / TC;
@@ -124,48 +168,85 @@ struct ReduceFused {
     for (int lj = 0; lj < LC; ++lj) {
       if (lj != lw) continue;
 #pragma unroll
-      for (int li = 0; li < LR; ++li) colbuf[tr + TR * li] = A[idx(li, lj)];
+      for (int li = 0; li < LR; ++li) colbuf[tr + TR * li] = get(A, li, lj);
     }
   }
 
   // One register pass of phase P: A <- A - vk wk^H - wk vk^H on the blocks
   // that reach the trailing part, part += A * vn (row partials).
   template <int P>
-  static __device__ __forceinline__ void pass(cx<R> (&A)[NLOC], const cx<R>* __restrict__ vk,
+  static __device__ __forceinline__ void pass(Regs& A, const cx<R>* __restrict__ vk,
                                               const cx<R>* __restrict__ wk,
                                               const cx<R>* __restrict__ vn, R (&part)[PV]) {
     constexpr int KR = P / RATIO;
     const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
-    cx<R> vr[LR], wr[LR];
-#pragma unroll
-    for (int li = KR; li < LR; ++li) {
-      vr[li] = vk[tr + TR * li];
-      wr[li] = wk[tr + TR * li];
-    }
 #pragma unroll
     for (int q = 0; q < PV; ++q) part[q] = R(0);
+    if constexpr (MF) {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, ii = lane & 15;
+      // global row of accumulator row ii of this wavefront's tiles
+      const int row = sizeof(R) == 8 ? 4 * wave + (ii & 3) + 32 * (ii >> 2)
+                                     : 4 * wave + (ii >> 2) + 32 * (ii & 3);
+      // A operand (row ii, k = g): -(vr, vi, wr, wi)[g] for the real part,
+      // -(vi, -vr, wi, -wr)[g] for the imaginary part
+      const R* ra = reinterpret_cast<const R*>(g < 2 ? vk : wk) + 2 * row;
+      const R aop_re = -ra[g & 1];
+      const R aop_im = (g & 1) ? ra[0] : -ra[1];
+      // B operand (k = g, column of this lane): (wr, wi, vr, vi)[g]
+      const R* rb = reinterpret_cast<const R*>(g < 2 ? wk : vk) + 2 * tc + (g & 1);
 #pragma unroll
-    for (int lj = P; lj < LC; ++lj) {
-      const int j = tc + TC * lj;
-      const cx<R> vc = vk[j], wc = wk[j], xc = vn[j];
+      for (int lj = P; lj < LC; ++lj) {
+        const R bop = rb[2 * TC * lj];
+        if constexpr (sizeof(R) == 8) {
+          A.re[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop_re, bop, A.re[lj], 0, 0, 0);
+          A.im[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop_im, bop, A.im[lj], 0, 0, 0);
+        } else {
+          A.re[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop_re, bop, A.re[lj], 0, 0, 0);
+          A.im[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop_im, bop, A.im[lj], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int lj = P; lj < LC; ++lj) {
+        const cx<R> xc = vn[tc + TC * lj];
+#pragma unroll
+        for (int li = KR; li < LR; ++li) {
+          const R are = A.re[lj][li], aim = A.im[lj][li];
+          part[2 * li] = fma(are, xc.re, part[2 * li]);
+          part[2 * li] = fma(-aim, xc.im, part[2 * li]);
+          part[2 * li + 1] = fma(are, xc.im, part[2 * li + 1]);
+          part[2 * li + 1] = fma(aim, xc.re, part[2 * li + 1]);
+        }
+      }
+    } else {
+      cx<R> vr[LR], wr[LR];
 #pragma unroll
       for (int li = KR; li < LR; ++li) {
-        cx<R> a = A[idx(li, lj)];
-        // a -= v_i conj(w_j) + w_i conj(v_j)
-        a.re = fma(-vr[li].re, wc.re, a.re);
-        a.re = fma(-vr[li].im, wc.im, a.re);
-        a.re = fma(-wr[li].re, vc.re, a.re);
-        a.re = fma(-wr[li].im, vc.im, a.re);
-        a.im = fma(-vr[li].im, wc.re, a.im);
-        a.im = fma(vr[li].re, wc.im, a.im);
-        a.im = fma(-wr[li].im, vc.re, a.im);
-        a.im = fma(wr[li].re, vc.im, a.im);
-        A[idx(li, lj)] = a;
-        // (A v)_i += a x_j
-        part[2 * li] = fma(a.re, xc.re, part[2 * li]);
-        part[2 * li] = fma(-a.im, xc.im, part[2 * li]);
-        part[2 * li + 1] = fma(a.re, xc.im, part[2 * li + 1]);
-        part[2 * li + 1] = fma(a.im, xc.re, part[2 * li + 1]);
+        vr[li] = vk[tr + TR * li];
+        wr[li] = wk[tr + TR * li];
+      }
+#pragma unroll
+      for (int lj = P; lj < LC; ++lj) {
+        const int j = tc + TC * lj;
+        const cx<R> vc = vk[j], wc = wk[j], xc = vn[j];
+#pragma unroll
+        for (int li = KR; li < LR; ++li) {
+          cx<R> a = get(A, li, lj);
+          // a -= v_i conj(w_j) + w_i conj(v_j)
+          a.re = fma(-vr[li].re, wc.re, a.re);
+          a.re = fma(-vr[li].im, wc.im, a.re);
+          a.re = fma(-wr[li].re, vc.re, a.re);
+          a.re = fma(-wr[li].im, vc.im, a.re);
+          a.im = fma(-vr[li].im, wc.re, a.im);
+          a.im = fma(vr[li].re, wc.im, a.im);
+          a.im = fma(-wr[li].im, vc.re, a.im);
+          a.im = fma(wr[li].re, vc.im, a.im);
+          set(A, li, lj, a);
+          // (A v)_i += a x_j
+          part[2 * li] = fma(a.re, xc.re, part[2 * li]);
+          part[2 * li] = fma(-a.im, xc.im, part[2 * li]);
+          part[2 * li + 1] = fma(a.re, xc.im, part[2 * li + 1]);
+          part[2 * li + 1] = fma(a.im, xc.re, part[2 * li + 1]);
+        }
       }
     }
   }
@@ -173,78 +254,76 @@ struct ReduceFused {
   // Step k (-1 <= k <= n-3) in phase P = (k+1)/TC: w_k, column k+1 of
   // A^{(k+1)}, reflector k+1, the fused register pass, y_{k+1}; one barrier.
   template <int P>
-  static __device__ __forceinline__ void step(const int n, const int k, cx<R> (&A)[NLOC],
-                                              Smem& sm, R& tre, R& tim) {
+  static __device__ __forceinline__ void step(const int n, const int k, Regs& A, Smem& sm, R& tre,
+                                              R& tim) {
     const int tid = threadIdx.x, tr = tid / TC, lane = tid & 63, wave = tid >> 6;
     const int lg = tid % TC;
     const int q_rs = reduce_scatter_index<TC, PV>(lg);
     const bool w_rs = reduce_scatter_writer<TC, PV>(lg);
     cx<R>* wb = sm.wb[wave];
     {
-      const int kb = k & 1, nb = (k + 1) & 1;
+      const int kb = k & 1, nb = (k + 1) & 1, k1 = k + 1;
       const cx<R>* vk = sm.vb[wave][kb];
       cx<R>* vn = sm.vb[wave][nb];
+      const cx<R>* yk = sm.y[kb];
+      const cx<R>* colk = sm.col[nb];
+      // Every LDS operand of the vector phase is read once, up front; entries
+      // outside rows k+1..n-1 are masked with selects (rows <= k of y_k and of
+      // the column buffer hold stale data), so the phase has no branches and
+      // a single LDS round trip.  For k = -1 the v_k buffer holds zeros.
+      cx<R> vv[NQ], yv[NQ], cv[NQ];
+      bool ok[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = lane + 64 * q;
+        const int ic = i < NP ? i : NP - 1;
+        vv[q] = vk[ic];
+        yv[q] = yk[ic];
+        cv[q] = colk[ic];
+        ok[q] = i > k && i < n;
+      }
       // ---- w_k = tau y_k - (|tau|^2/2) Re(v_k^H y_k) v_k   (rows k+1..n-1)
       cx<R> wreg[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) wreg[q] = {R(0), R(0)};
+      cx<R> wk1 = {R(0), R(0)};  // w_k[k+1], the same in every lane
       if (k >= 0) {
-        const cx<R>* yk = sm.y[kb];
         R c = R(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const int i = lane + 64 * q;
-          if (i > k && i < n) {  // rows <= k of y_k hold stale data
-            const cx<R> v = vk[i], yy = yk[i];
-            c = fma(v.re, yy.re, c);
-            c = fma(v.im, yy.im, c);
-          }
+          const R t = fma(vv[q].re, yv[q].re, vv[q].im * yv[q].im);
+          c += ok[q] ? t : R(0);
         }
         c = wave_total(c);
         const R a2 = R(0.5) * (tre * tre + tim * tim) * c;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
+          const R wr_ = fma(tre, yv[q].re, fma(-tim, yv[q].im, -a2 * vv[q].re));
+          const R wi_ = fma(tre, yv[q].im, fma(tim, yv[q].re, -a2 * vv[q].im));
+          wreg[q] = {ok[q] ? wr_ : R(0), ok[q] ? wi_ : R(0)};
           const int i = lane + 64 * q;
-          cx<R> w = {R(0), R(0)};
-          if (i > k && i < n) {
-            const cx<R> v = vk[i], yy = yk[i];
-            w.re = fma(tre, yy.re, fma(-tim, yy.im, -a2 * v.re));
-            w.im = fma(tre, yy.im, fma(tim, yy.re, -a2 * v.im));
-          }
-          wreg[q] = w;
-          if (i < NP) wb[i] = w;
+          if (NP % 64 == 0 || i < NP) wb[i] = wreg[q];
         }
-      } else {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) wreg[q] = {R(0), R(0)};
+        wk1 = bcast(wreg, k1);
       }
       // ---- column k+1 of A^{(k+1)}: x_i = col_i - v_k[i] conj(w_k[k+1]) - w_k[i]  (v_k[k+1] = 1)
-      const cx<R>* colk = sm.col[nb];
-      cx<R> wk1 = {R(0), R(0)};  // w_k[k+1], the same in every lane
-      if (k >= 0) wk1 = bcast(wreg, k + 1);
       cx<R> xreg[NQ];
       R s2 = R(0);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
+        const cx<R> v = vv[q], w = wreg[q], c = cv[q];
+        const R xr = fma(-v.re, wk1.re, fma(-v.im, wk1.im, c.re - w.re));
+        const R xi = fma(-v.im, wk1.re, fma(v.re, wk1.im, c.im - w.im));
+        xreg[q] = {ok[q] ? xr : R(0), ok[q] ? xi : R(0)};
         const int i = lane + 64 * q;
-        cx<R> x = {R(0), R(0)};
-        if (i > k && i < n) {
-          const cx<R> c = colk[i];
-          const cx<R> v = k >= 0 ? vk[i] : cx<R>{R(0), R(0)};
-          const cx<R> w = wreg[q];
-          // x = c - v conj(wk1) - w
-          x.re = fma(-v.re, wk1.re, fma(-v.im, wk1.im, c.re - w.re));
-          x.im = fma(-v.im, wk1.re, fma(v.re, wk1.im, c.im - w.im));
-          if (i > k + 2) s2 = fma(x.re, x.re, fma(x.im, x.im, s2));
-        }
-        xreg[q] = x;
+        const R t = fma(xreg[q].re, xreg[q].re, xreg[q].im * xreg[q].im);
+        s2 += i > k + 2 ? t : R(0);
       }
       s2 = wave_total(s2);
-      const int k1 = k + 1;
       const cx<R> x1 = bcast(xreg, k1);
       if (tid == 0) sm.d[k1] = (double)x1.re;
       cx<R> al = {R(0), R(0)};
-      if (k1 + 1 < n) {
-        al = bcast(xreg, k1 + 1);
-      }
+      if (k1 + 1 < n) al = bcast(xreg, k1 + 1);
       // ---- reflector k+1 from x[k+2..n-1] (none for the last column pair)
       R scr = R(0), sci = R(0);
       const bool refl = (k1 <= n - 3);
@@ -271,18 +350,11 @@ struct ReduceFused {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int i = lane + 64 * q;
-        if (i < NP) {
-          cx<R> v = {R(0), R(0)};
-          if (refl) {
-            if (i == k1 + 1) {
-              v.re = R(1);
-            } else if (i > k1 + 1 && i < n) {
-              const cx<R> x = xreg[q];
-              v = {fma(x.re, scr, -x.im * sci), fma(x.re, sci, x.im * scr)};
-            }
-          }
-          vn[i] = v;
-        }
+        const cx<R> x = xreg[q];
+        const R sr_ = fma(x.re, scr, -x.im * sci), si_ = fma(x.re, sci, x.im * scr);
+        const bool head = refl && i == k1 + 1, tail = refl && i > k1 + 1 && i < n;
+        const cx<R> v = {head ? R(1) : (tail ? sr_ : R(0)), tail ? si_ : R(0)};
+        if (NP % 64 == 0 || i < NP) vn[i] = v;
       }
       wave_lds_fence();
       // ---- fused pass: A^{(k+1)} = A^{(k)} - v_k w_k^H - w_k v_k^H,  part = A^{(k+1)} v_{k+1}
@@ -307,8 +379,8 @@ struct ReduceFused {
 
   // Steps of phase P and every later phase; k advances to n-2.
   template <int P>
-  static __device__ __forceinline__ void phases(const int n, int& k, cx<R> (&A)[NLOC], Smem& sm,
-                                                R& tre, R& tim) {
+  static __device__ __forceinline__ void phases(const int n, int& k, Regs& A, Smem& sm, R& tre,
+                                                R& tim) {
     if constexpr (P < LC) {
       const int kend = (P + 1) * TC - 2 < n - 3 ? (P + 1) * TC - 2 : n - 3;  // last k of phase P
       for (; k <= kend; ++k) step<P>(n, k, A, sm, tre, tim);
@@ -316,7 +388,7 @@ struct ReduceFused {
     }
   }
 
-  static __device__ void run(const int n, cx<R> (&A)[NLOC], Smem& sm, double* __restrict__ dg,
+  static __device__ void run(const int n, Regs& A, Smem& sm, double* __restrict__ dg,
                              double* __restrict__ e2g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // v_{-1} = w_{-1} = 0

@@ -32,6 +32,7 @@ struct ReduceLower {
   static constexpr int NW = NT / 64;          // wavefronts per workgroup
   static constexpr int NP = G * LR;           // padded dimension
   static constexpr int NLOC = LR * (LR + 1) / 2;
+  typedef cx<R> Regs[NLOC];
   static constexpr int PITCH = NP + 1;        // LDS row pitch of partial sums
   static_assert(NT % 64 == 0, "workgroup must be whole wavefronts");
 

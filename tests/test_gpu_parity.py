@@ -316,3 +316,48 @@ def test_autotuner_reports_choices(lib):
     rep = lat.tuning_report()
     assert "n=128" in rep and "fp64" in rep
     lat.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("n", [32, 50, 72, 128])
+def test_every_reducer_variant(lib, n, precision):
+    """Each reducer variant the autotuner may pick gives the LAPACK spectrum
+    (FP64 to 1e-12 of the spectral scale, mixed to the FP32 bound), on random
+    Hermitian matrices of a ragged dimension."""
+    names = lib.tca_reducer_variants(n, precision)
+    A = np.stack([rand_hermitian(n, 40 + s) for s in range(3)])
+    ref = np.stack([np.linalg.eigvalsh(a) for a in A])
+    scale = np.max(np.abs(ref))
+    # FP64 as test_heevals_random_fp64; FP32 as test_heevals_mixed_precision
+    tol = 1e-12 * max(1.0, n / 32) if precision == 0 else 2e-5 * np.sqrt(n)
+    try:
+        for v, name in enumerate(names):
+            lib.tca_select_reducer_variant(n, precision, v)
+            w, _ = lib.tca_heevals_batched(A, precision=precision)
+            assert np.max(np.abs(np.sort(w, axis=1) - ref)) <= tol * max(1.0, scale), name
+    finally:
+        lib.tca_select_reducer_variant(n, precision, 0)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_reducer_variants_lockstep_8x8_cluster(lib, variant):
+    """Sampled lockstep replay of a 32x32 / 8x8 sweep with each FP64 reducer variant."""
+    names = lib.tca_reducer_variants(128, 0)
+    if variant >= len(names):
+        pytest.skip("no such variant")
+    lib.tca_select_reducer_variant(128, 0, variant)
+    try:
+        L, Lc, T, seed = 32, 8, 0.05, 3
+        lat = lib.Lattice(L, Lc, seed=seed, JAF=0.05)
+        S0 = lat.spins()
+        recs, _ = lat.sweep([T], log=True)
+        S1 = lat.spins()
+        lat.close()
+        prm = otca.Params(L=L, Lc=Lc, JAF=0.05, seed=seed)
+        rng = np.random.default_rng(variant)
+        check = set(rng.choice(L * L, 16, replace=False).tolist())
+        S_or, st = otca.replay_sweep(S0, prm, T, 0, recs_to_dicts(recs), check=check)
+        assert st["bad"] == 0 and st["max_rel"] <= REL_TOL, names[variant]
+        assert np.array_equal(S_or, S1)
+    finally:
+        lib.tca_select_reducer_variant(128, 0, 0)
