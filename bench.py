@@ -29,11 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix): 256 CU x 2.4 GHz x 128 flop/clk/CU
-PEAK_FP32_VALU_TFLOPS = 78.6   # FP32 vector without packed math, same issue rate as FP64
-# HBM bytes per launch of the FP64 fused reduction at the headline workload, from the
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk/CU
+# HBM bytes per launch of the autotuned FP64 reduction (fused, rank-2 update on MFMA) at the
+# headline workload, from the
 # FETCH_SIZE / WRITE_SIZE counters of `bench.py --counter-run` scaled by the calibration
 # transfers (FETCH_SIZE x 1.996, WRITE_SIZE x 1.0); re-measure whenever the kernel changes.
-TRAFFIC_BYTES_FP64_REDUCE = 2.48e6
+TRAFFIC_BYTES_FP64_REDUCE = 5.06e6
 
 
 def reduce_flops(n):
@@ -56,6 +57,7 @@ def parse():
                     help="for hardware-counter runs: two FP64 sweeps of the headline workload, then "
                          "a 64 MiB fill and a 64 MiB sum whose byte counts calibrate FETCH_SIZE and "
                          "WRITE_SIZE; prints no JSON")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--sq-check-sweeps", type=int, default=40,
                     help="anneal length of the S(q) comparison of the two chains (0 = skip)")
     return ap.parse_args()
@@ -91,6 +93,31 @@ def cpu_baseline(otca, L, Lc, JAF, seed, T, nsweeps):
             S, _ = otca.sweep_sequential(S, prm, T, sw)
         dt = time.perf_counter() - t0
     return L * L * nsweeps / dt, dt
+
+
+def batched_uneven(tca, stream):
+    """Uneven cluster sizes: 100x100 lattice, sizes drawn per update from
+    {6x6, 8x8, 10x10} (n = 72, 128, 200), J_AF = 0.05, T = 0.05; one reduction
+    launch per size class per block (largest first), graph-replayed sweeps."""
+    out = {"workload": "100x100 lattice, cluster sizes {6,8,10} drawn per update, J_AF=0.05, T=0.05"}
+    for name, prec in (("fp64", tca.TCA_FP64), ("mixed", tca.TCA_MIXED)):
+        lat = tca.Lattice(100, 8, seed=21, JAF=0.05, precision=prec, Lc_classes=(6, 8, 10),
+                          stream=stream)
+        lat.sweep([0.05])
+        t0 = time.perf_counter()
+        _, st = lat.sweep([0.05] * 4)
+        dt = time.perf_counter() - t0
+        rep = lat.tuning_report()
+        lat.close()
+        prof = tca.Lattice(100, 8, seed=21, JAF=0.05, precision=prec, Lc_classes=(6, 8, 10),
+                           flags=tca.TCA_FLAG_PROFILE, stream=stream)
+        _, sp = prof.sweep([0.05] * 2)
+        prof.close()
+        out[name] = {"updates_per_s": st["updates"] / dt,
+                     "ms_per_sweep": {"reduce_all_classes": sp["reduce_ms"] / 2,
+                                      "eigenvalues": sp["eig_ms"] / 2, "decide": sp["decide_ms"] / 2},
+                     "autotuner": rep.strip().splitlines()}
+    return out
 
 
 def full_form(tca, a, stream):
@@ -202,11 +229,10 @@ def main():
     h = L // 2
     torch.cuda.set_device(0)
     if a.counter_run:
-        lat = tca.Lattice(L, Lc, seed=seed, JH=8.0, JAF=JAF, flags=tca.TCA_FLAG_NO_AUTOTUNE)
+        lat = tca.Lattice(L, Lc, seed=seed, JH=8.0, JAF=JAF)   # autotuned, as in the bench
         lat.sweep([T, T])
         lat.close()
-        x = torch.empty(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        x.fill_(1.0)
+        x = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")  # elementwise fill
         s = x.sum()
         torch.cuda.synchronize()
         print(f"counter run done ({float(s):.0f})", file=sys.stderr)
@@ -258,6 +284,7 @@ def main():
                          f"eigenvalues, one thread, {secs:.1f} s"}
 
     ff = None if a.no_full_form else full_form(tca, a, stream)
+    un = None if a.no_uneven else batched_uneven(tca, stream)
 
     out = {
         "metric": "cluster diagonalizations & exact-equivalent MC updates/sec at 8×8 cluster; ΔF err",
@@ -291,10 +318,12 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": TRAFFIC_BYTES_FP64_REDUCE,
-                     "kernel": "cluster_block_reduce<ReduceFused<32,16,4,8,double>>",
+                     "kernel": "cluster_block_reduce, n=128 FP64, autotuned: "
+                               + report.strip().splitlines()[0].split("-> ")[-1],
                      "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "full_form": ff,
+        "batched_uneven": un,
     }
     print(json.dumps(out))
 

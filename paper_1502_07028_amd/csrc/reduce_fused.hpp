@@ -53,6 +53,15 @@ __device__ __forceinline__ float fast_rcp(float x) {
   return fmaf(r, e, r);
 }
 
+// f(integral_constant<int, I>) for I = B .. E-1
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 template <typename R>
 struct Vec4Of;
 template <>
@@ -194,8 +203,10 @@ struct ReduceFused {
       const R aop_im = (g & 1) ? ra[0] : -ra[1];
       // B operand (k = g, column of this lane): (wr, wi, vr, vi)[g]
       const R* rb = reinterpret_cast<const R*>(g < 2 ? wk : vk) + 2 * tc + (g & 1);
-#pragma unroll
-      for (int lj = P; lj < LC; ++lj) {
+      // tile lj + 1 goes to the matrix cores while the vector ALUs form the
+      // product of tile lj
+      auto update = [&](auto LJ) {
+        constexpr int lj = decltype(LJ)::value;
         const R bop = rb[2 * TC * lj];
         if constexpr (sizeof(R) == 8) {
           A.re[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop_re, bop, A.re[lj], 0, 0, 0);
@@ -204,9 +215,9 @@ struct ReduceFused {
           A.re[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop_re, bop, A.re[lj], 0, 0, 0);
           A.im[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop_im, bop, A.im[lj], 0, 0, 0);
         }
-      }
-#pragma unroll
-      for (int lj = P; lj < LC; ++lj) {
+      };
+      auto product = [&](auto LJ) {
+        constexpr int lj = decltype(LJ)::value;
         const cx<R> xc = vn[tc + TC * lj];
 #pragma unroll
         for (int li = KR; li < LR; ++li) {
@@ -216,7 +227,13 @@ struct ReduceFused {
           part[2 * li + 1] = fma(are, xc.im, part[2 * li + 1]);
           part[2 * li + 1] = fma(aim, xc.re, part[2 * li + 1]);
         }
-      }
+      };
+      update(std::integral_constant<int, P>{});
+      static_for<P, LC>([&](auto LJ) {
+        constexpr int lj = decltype(LJ)::value;
+        if constexpr (lj + 1 < LC) update(std::integral_constant<int, lj + 1>{});
+        product(LJ);
+      });
     } else {
       cx<R> vr[LR], wr[LR];
 #pragma unroll
@@ -271,7 +288,7 @@ struct ReduceFused {
       // outside rows k+1..n-1 are masked with selects (rows <= k of y_k and of
       // the column buffer hold stale data), so the phase has no branches and
       // a single LDS round trip.  For k = -1 the v_k buffer holds zeros.
-      cx<R> vv[NQ], yv[NQ], cv[NQ];
+      cx<R> vv[NQ], yv[NQ];
       bool ok[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -279,7 +296,6 @@ struct ReduceFused {
         const int ic = i < NP ? i : NP - 1;
         vv[q] = vk[ic];
         yv[q] = yk[ic];
-        cv[q] = colk[ic];
         ok[q] = i > k && i < n;
       }
       // ---- w_k = tau y_k - (|tau|^2/2) Re(v_k^H y_k) v_k   (rows k+1..n-1)
@@ -311,7 +327,8 @@ struct ReduceFused {
       R s2 = R(0);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const cx<R> v = vv[q], w = wreg[q], c = cv[q];
+        const int ic = lane + 64 * q < NP ? lane + 64 * q : NP - 1;
+        const cx<R> v = vv[q], w = wreg[q], c = colk[ic];
         const R xr = fma(-v.re, wk1.re, fma(-v.im, wk1.im, c.re - w.re));
         const R xi = fma(-v.im, wk1.re, fma(v.re, wk1.im, c.im - w.im));
         xreg[q] = {ok[q] ? xr : R(0), ok[q] ? xi : R(0)};
