@@ -263,8 +263,14 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
                : v == 2 ? f(ReduceFull<32, 16, 4, 8, R>{}, R{})
                : v == 3 ? f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{})
                         : f(ReduceFused<32, 16, 4, 8, R, 2, true>{}, R{});
-      case 4: return v == 0 ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{}) : f(ReduceFull<32, 16, 6, 11, R>{}, R{});
-      case 5: return v == 0 ? f(ReduceFused<32, 16, 7, 13, R, 2>{}, R{}) : f(ReduceFull<32, 16, 7, 13, R>{}, R{});
+      case 4:
+        return v == 0   ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{})
+               : v == 1 ? f(ReduceFull<32, 16, 6, 11, R>{}, R{})
+                        : f(ReduceLower<32, 6, R>{}, R{});
+      case 5:
+        return v == 0   ? f(ReduceFused<32, 16, 7, 13, R, 2>{}, R{})
+               : v == 1 ? f(ReduceFull<32, 16, 7, 13, R>{}, R{})
+                        : f(ReduceLower<32, 7, R>{}, R{});
     }
   } else {
     using R = double;
@@ -297,8 +303,8 @@ static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
      {"fused 32x16 grid, 2 workgroups/CU", "fused 32x16 grid, 1 workgroup/CU",
       "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
       "fused 32x16 grid, rank-2 update on MFMA, 1 workgroup/CU"},
-     {"fused 32x16 grid", "two-pass 32x16 grid"},
-     {"fused 32x16 grid", "two-pass 32x16 grid"}}};
+     {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"},
+     {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"}}};
 
 static std::atomic<int> g_choice[2][kNumReducerClasses];
 
