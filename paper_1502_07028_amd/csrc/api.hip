@@ -126,9 +126,9 @@ static int autotune(tca_ctx* c) {
     const int cls = reducer_class(n);
     const int nv = reducer_variants(cls, c->p.precision);
     if (!g_tuned[prec][cls] && nv > 1) {
-      char line[512];
-      int off = snprintf(line, sizeof(line), "n=%d %s (%d matrices):", n,
-                         prec ? "mixed" : "fp64", 2 * hh);
+      char buf[160];
+      snprintf(buf, sizeof(buf), "n=%d %s (%d matrices):", n, prec ? "mixed" : "fp64", 2 * hh);
+      std::string line = buf;
       double best_ms = 1e300;
       int best = 0;
       for (int v = 0; v < nv; ++v) {
@@ -145,15 +145,15 @@ static int autotune(tca_ctx* c) {
         float ms = 0.f;
         TCA_CK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
         const double per = ms / 3.0;
-        off += snprintf(line + off, sizeof(line) - (size_t)off, " %s %.3f ms;",
-                        reducer_name(cls, c->p.precision, v), per);
+        snprintf(buf, sizeof(buf), " %s %.3f ms;", reducer_name(cls, c->p.precision, v), per);
+        line += buf;
         if (per < best_ms) {
           best_ms = per;
           best = v;
         }
       }
-      snprintf(line + off, sizeof(line) - (size_t)off, " -> %s",
-               reducer_name(cls, c->p.precision, best));
+      line += " -> ";
+      line += reducer_name(cls, c->p.precision, best);
       set_reducer_choice(cls, c->p.precision, best);
       g_tuned[prec][cls] = true;
       g_tune_log[prec][cls] = line;

@@ -23,6 +23,7 @@
 #include "reduce_full.hpp"
 #include "reduce_fused.hpp"
 #include "reduce_lower.hpp"
+#include "reduce_split.hpp"
 #include "rng.hpp"
 #include "tridiag.hpp"
 
@@ -255,14 +256,24 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
     using R = float;
     switch (cls) {
       case 0: return v == 0 ? f(ReduceFused<8, 8, 4, 4, R>{}, R{}) : f(ReduceFull<8, 8, 4, 4, R>{}, R{});
-      case 1: return v == 0 ? f(ReduceFused<16, 16, 4, 4, R>{}, R{}) : f(ReduceFull<16, 16, 4, 4, R>{}, R{});
-      case 2: return v == 0 ? f(ReduceFused<16, 16, 5, 5, R>{}, R{}) : f(ReduceFull<16, 16, 5, 5, R>{}, R{});
+      case 1:
+        return v == 0   ? f(ReduceFused<16, 16, 4, 4, R>{}, R{})
+               : v == 1 ? f(ReduceFull<16, 16, 4, 4, R>{}, R{})
+                        : f(ReduceSplit<16, 16, 4, 4, R>{}, R{});
+      case 2:
+        return v == 0   ? f(ReduceFused<16, 16, 5, 5, R>{}, R{})
+               : v == 1 ? f(ReduceFull<16, 16, 5, 5, R>{}, R{})
+                        : f(ReduceSplit<16, 16, 5, 5, R>{}, R{});
       case 3:
         return v == 0   ? f(ReduceFused<32, 16, 4, 8, R>{}, R{})
                : v == 1 ? f(ReduceFused<32, 16, 4, 8, R, 2>{}, R{})
                : v == 2 ? f(ReduceFull<32, 16, 4, 8, R>{}, R{})
                : v == 3 ? f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{})
-                        : f(ReduceFused<32, 16, 4, 8, R, 2, true>{}, R{});
+               : v == 4 ? f(ReduceFused<32, 16, 4, 8, R, 2, true>{}, R{})
+               : v == 5 ? f(ReduceSplit<32, 16, 4, 8, R, 2>{}, R{})
+               : v == 6 ? f(ReduceSplit<32, 16, 4, 8, R, 2, true>{}, R{})
+               : v == 7 ? f(ReduceSplit<16, 16, 8, 8, R, 2>{}, R{})
+                        : f(ReduceFused<16, 16, 8, 8, R, 2>{}, R{});
       case 4:
         return v == 0   ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{})
                : v == 1 ? f(ReduceFull<32, 16, 6, 11, R>{}, R{})
@@ -276,12 +287,20 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
     using R = double;
     switch (cls) {
       case 0: return v == 0 ? f(ReduceFused<8, 8, 4, 4, R>{}, R{}) : f(ReduceFull<8, 8, 4, 4, R>{}, R{});
-      case 1: return v == 0 ? f(ReduceFused<16, 16, 4, 4, R>{}, R{}) : f(ReduceFull<16, 16, 4, 4, R>{}, R{});
-      case 2: return v == 0 ? f(ReduceFused<16, 16, 5, 5, R>{}, R{}) : f(ReduceFull<16, 16, 5, 5, R>{}, R{});
+      case 1:
+        return v == 0   ? f(ReduceFused<16, 16, 4, 4, R>{}, R{})
+               : v == 1 ? f(ReduceFull<16, 16, 4, 4, R>{}, R{})
+                        : f(ReduceSplit<16, 16, 4, 4, R>{}, R{});
+      case 2:
+        return v == 0   ? f(ReduceFused<16, 16, 5, 5, R>{}, R{})
+               : v == 1 ? f(ReduceFull<16, 16, 5, 5, R>{}, R{})
+                        : f(ReduceSplit<16, 16, 5, 5, R>{}, R{});
       case 3:
         return v == 0   ? f(ReduceFused<32, 16, 4, 8, R>{}, R{})
                : v == 1 ? f(ReduceFull<32, 16, 4, 8, R>{}, R{})
-                        : f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{});
+               : v == 2 ? f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{})
+               : v == 3 ? f(ReduceSplit<32, 16, 4, 8, R>{}, R{})
+                        : f(ReduceSplit<32, 16, 4, 8, R, 0, true>{}, R{});
       case 4: return f(ReduceLower<16, 11, R>{}, R{});
       case 5: return f(ReduceLower<16, 13, R>{}, R{});
     }
@@ -289,20 +308,24 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
   return hipErrorInvalidValue;
 }
 
-constexpr int kMaxVariants = 5;
+constexpr int kMaxVariants = 9;
 static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
     {{"fused 8x8 grid", "two-pass 8x8 grid"},
-     {"fused 16x16 grid", "two-pass 16x16 grid"},
-     {"fused 16x16 grid", "two-pass 16x16 grid"},
-     {"fused 32x16 grid", "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA"},
+     {"fused 16x16 grid", "two-pass 16x16 grid", "split 16x16 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid", "split 16x16 grid"},
+     {"fused 32x16 grid", "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA",
+      "split 32x16 grid", "split 32x16 grid, rank-2 update on MFMA"},
      {"lower-triangle 16x16 grid"},
      {"lower-triangle 16x16 grid"}},
     {{"fused 8x8 grid", "two-pass 8x8 grid"},
-     {"fused 16x16 grid", "two-pass 16x16 grid"},
-     {"fused 16x16 grid", "two-pass 16x16 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid", "split 16x16 grid"},
+     {"fused 16x16 grid", "two-pass 16x16 grid", "split 16x16 grid"},
      {"fused 32x16 grid, 2 workgroups/CU", "fused 32x16 grid, 1 workgroup/CU",
       "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
-      "fused 32x16 grid, rank-2 update on MFMA, 1 workgroup/CU"},
+      "fused 32x16 grid, rank-2 update on MFMA, 1 workgroup/CU",
+      "split 32x16 grid, 2 workgroups/CU",
+      "split 32x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
+      "split 16x16 grid, 2 workgroups/CU", "fused 16x16 grid, 2 workgroups/CU"},
      {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"},
      {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"}}};
 

@@ -230,8 +230,8 @@ struct ReduceFull {
   }
 
   // Reduce A (registers) to (d, e2) in global memory.
-  static __device__ void run(const int n, cx<R> (&A)[NLOC], Smem& sm, double* __restrict__ dg,
-                             double* __restrict__ e2g) {
+  static __device__ __forceinline__ void run(const int n, cx<R> (&A)[NLOC], Smem& sm,
+                                             double* __restrict__ dg, double* __restrict__ e2g) {
     const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC, lane = tid & 63, wave = tid >> 6;
     const int lg = tid % TC;  // lane within the row group
     double* d = sm.d;

@@ -405,8 +405,8 @@ struct ReduceFused {
     }
   }
 
-  static __device__ void run(const int n, Regs& A, Smem& sm, double* __restrict__ dg,
-                             double* __restrict__ e2g) {
+  static __device__ __forceinline__ void run(const int n, Regs& A, Smem& sm,
+                                             double* __restrict__ dg, double* __restrict__ e2g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // v_{-1} = w_{-1} = 0
     for (int i = lane; i < NP; i += 64) {

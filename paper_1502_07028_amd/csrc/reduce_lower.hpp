@@ -92,8 +92,8 @@ struct ReduceLower {
   }
 
   // Householder reduction to (d, e2); leaves them in LDS.
-  static __device__ void run(const int n, cx<R> (&A)[NLOC], Smem& sm, double* __restrict__ dg,
-                             double* __restrict__ e2g) {
+  static __device__ __forceinline__ void run(const int n, cx<R> (&A)[NLOC], Smem& sm,
+                                             double* __restrict__ dg, double* __restrict__ e2g) {
     double* d = sm.d;
     double* e2 = sm.e2;
     const int tid = threadIdx.x, tr = tid / G, tc = tid % G, lane = tid & 63;

@@ -339,7 +339,44 @@ def test_every_reducer_variant(lib, n, precision):
         lib.tca_select_reducer_variant(n, precision, 0)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+def _cluster_matrices(Lc):
+    rng = np.random.default_rng(Lc)
+    Nc = Lc * Lc
+    mats = []
+    for _ in range(2):
+        sp = rng.normal(size=(Nc, 3))
+        mats.append(sp / np.linalg.norm(sp, axis=1, keepdims=True))
+    mats.append(np.tile([0.0, 0.0, 1.0], (Nc, 1)))                       # ferromagnet
+    sgn = np.array([(-1) ** ((l % Lc) + (l // Lc)) for l in range(Nc)], float)
+    mats.append(np.outer(sgn, [0.0, 0.0, 1.0]))                           # Neel
+    mats.append(np.tile([0.6, 0.0, 0.8], (Nc, 1)))                        # tilted ferromagnet
+    return np.stack([model.cluster_hamiltonian(sp, Lc, 1.0, 8.0) for sp in mats])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("Lc", [5, 6, 8, 10])
+def test_every_reducer_variant_cluster_matrices(lib, Lc, precision):
+    """Each reducer variant on cluster Hamiltonians (sparse columns with exact
+    zeros, degenerate spectra: random, ferromagnetic, Neel and tilted spins)."""
+    n = 2 * Lc * Lc
+    names = lib.tca_reducer_variants(n, precision)
+    A = _cluster_matrices(Lc)
+    ref = np.stack([np.linalg.eigvalsh(a) for a in A])
+    tol = (1e-12 * max(1.0, n / 32) if precision == 0 else 2e-5 * np.sqrt(n)) * np.max(np.abs(ref))
+    bad = []
+    try:
+        for v, name in enumerate(names):
+            lib.tca_select_reducer_variant(n, precision, v)
+            w, _ = lib.tca_heevals_batched(A, precision=precision)
+            err = np.max(np.abs(np.sort(w, axis=1) - ref), axis=1)
+            if not np.all(err <= tol):
+                bad.append((name, err.tolist()))
+        assert not bad, bad
+    finally:
+        lib.tca_select_reducer_variant(n, precision, 0)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_reducer_variants_lockstep_8x8_cluster(lib, variant):
     """Sampled lockstep replay of a 32x32 / 8x8 sweep with each FP64 reducer variant."""
     names = lib.tca_reducer_variants(128, 0)
