@@ -14,9 +14,11 @@
 //   (3) update  A^{(k+1)} = A^{(k)} - v_k w_k^H - w_k v_k^H       (registers)
 //   (4) product y_{k+1} = A^{(k+1)} v_{k+1}, row reduce-scatter, barrier.
 // (2) and (3) are independent.  With MF the update is a pair of MFMA
-// products per 16 x 16 tile, issued before (2) so that the matrix cores work
-// while the vector ALUs build the reflector; otherwise (2) runs first, which
-// keeps the register update and the product back to back.
+// products per 16 x 16 tile, all operands read from LDS first and the MFMAs
+// issued before (2), so that the matrix cores work while the vector ALUs
+// build the reflector (issuing them in groups between the parts of (2),
+// pinned by scheduling barriers, measured slower); otherwise (2) runs first,
+// which keeps the register update and the product together.
 //
 // Less vector work per step.
 //  - Buffers are cleared once, so v_k vanishes outside rows k+1..n-1 and y_k
@@ -122,6 +124,44 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
   static_assert(TC == 16, "row groups of 16 lanes");
   static_assert(2 * LR <= 16, "at most 16 row values per lane");
 
+  // MFMA operands of the rank-2 update of phase P: row components of v and w
+  // (A operand, negated) and the column components of w and v of every
+  // active column block (B operand), read from LDS once.
+  struct MfOps {
+    R aop_re, aop_im;
+    R bop[LC];
+  };
+  template <int P>
+  static __device__ __forceinline__ MfOps mf_ops(const cx<R>* __restrict__ vk,
+                                                 const cx<R>* __restrict__ wk) {
+    const int tc = threadIdx.x % TC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, ii = lane & 15;
+    const int row = sizeof(R) == 8 ? 4 * wave + (ii & 3) + 32 * (ii >> 2)
+                                   : 4 * wave + (ii >> 2) + 32 * (ii & 3);
+    const R* ra = reinterpret_cast<const R*>(g < 2 ? vk : wk) + 2 * row;
+    const R* rb = reinterpret_cast<const R*>(g < 2 ? wk : vk) + 2 * tc + (g & 1);
+    MfOps o;
+    o.aop_re = -ra[g & 1];
+    o.aop_im = (g & 1) ? ra[0] : -ra[1];
+#pragma unroll
+    for (int lj = P; lj < LC; ++lj) o.bop[lj] = rb[2 * TC * lj];
+    return o;
+  }
+  // Issue the update MFMAs of column blocks J0 .. J1-1.
+  template <int J0, int J1>
+  static __device__ __forceinline__ void mf_tiles(Regs& A, const MfOps& o) {
+    static_for<J0, J1>([&](auto LJ) {
+      constexpr int lj = decltype(LJ)::value;
+      if constexpr (sizeof(R) == 8) {
+        A.re[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.aop_re, o.bop[lj], A.re[lj], 0, 0, 0);
+        A.im[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.aop_im, o.bop[lj], A.im[lj], 0, 0, 0);
+      } else {
+        A.re[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.aop_re, o.bop[lj], A.re[lj], 0, 0, 0);
+        A.im[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.aop_im, o.bop[lj], A.im[lj], 0, 0, 0);
+      }
+    });
+  }
+
   // A <- A - vk wk^H - wk vk^H on the blocks of phase P.
   template <int P>
   static __device__ __forceinline__ void update(Regs& A, const cx<R>* __restrict__ vk,
@@ -129,24 +169,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
     constexpr int KR = P / RATIO;
     const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
     if constexpr (MF) {
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, ii = lane & 15;
-      const int row = sizeof(R) == 8 ? 4 * wave + (ii & 3) + 32 * (ii >> 2)
-                                     : 4 * wave + (ii >> 2) + 32 * (ii & 3);
-      const R* ra = reinterpret_cast<const R*>(g < 2 ? vk : wk) + 2 * row;
-      const R aop_re = -ra[g & 1];
-      const R aop_im = (g & 1) ? ra[0] : -ra[1];
-      const R* rb = reinterpret_cast<const R*>(g < 2 ? wk : vk) + 2 * tc + (g & 1);
-      static_for<P, LC>([&](auto LJ) {
-        constexpr int lj = decltype(LJ)::value;
-        const R bop = rb[2 * TC * lj];
-        if constexpr (sizeof(R) == 8) {
-          A.re[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop_re, bop, A.re[lj], 0, 0, 0);
-          A.im[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop_im, bop, A.im[lj], 0, 0, 0);
-        } else {
-          A.re[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop_re, bop, A.re[lj], 0, 0, 0);
-          A.im[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop_im, bop, A.im[lj], 0, 0, 0);
-        }
-      });
+      mf_tiles<P, LC>(A, mf_ops<P>(vk, wk));
     } else {
       cx<R> vr[LR], wr[LR];
 #pragma unroll
@@ -171,6 +194,24 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
           a.im = fma(wr[li].re, vc.im, a.im);
           Base::set(A, li, lj, a);
         }
+      }
+    }
+  }
+
+  // Column wc (= k+2) of the registers -> colbuf.  In phase P it lies in
+  // column block P, or in block P+1 at the phase's last step: the two
+  // candidates are selected, so register indices stay static.
+  template <int P>
+  static __device__ __forceinline__ void store_next_col(const Regs& A, const int wc,
+                                                        cx<R>* __restrict__ colbuf) {
+    constexpr int P1 = P + 1 < LC ? P + 1 : P;
+    const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
+    const bool in_p = wc < TC * (P + 1);
+    if (tc == wc % TC) {
+#pragma unroll
+      for (int li = 0; li < LR; ++li) {
+        const cx<R> a = Base::get(A, li, P), b = Base::get(A, li, P1);
+        colbuf[tr + TR * li] = {in_p ? a.re : b.re, in_p ? a.im : b.im};
       }
     }
   }
@@ -214,14 +255,22 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
     const cx<R> wk1 = {fma(tre, y1.re, fma(-tim, y1.im, -a2)), fma(tre, y1.im, tim * y1.re)};
     const cx<R> wk2 = {fma(tre, y2.re, fma(-tim, y2.im, -a2 * v2.re)),
                        fma(tre, y2.im, fma(tim, y2.re, -a2 * v2.im))};
+    cx<R> cv[NQ], vv[NQ], wv[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      const int ic = i < NP ? i : NP - 1;
+      cv[q] = colk[ic];
+      vv[q] = vk[ic];
+      wv[q] = wb[ic];
+    }
     // x_i = col_i - v_k[i] conj(w_k[k+1]) - w_k[i]
     cx<R> xreg[NQ];
     R s2 = R(0);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int i = lane + 64 * q;
-      const int ic = i < NP ? i : NP - 1;
-      const cx<R> c = colk[ic], v = vk[ic], w = wb[ic];
+      const cx<R> c = cv[q], v = vv[q], w = wv[q];
       xreg[q].re = fma(-v.re, wk1.re, fma(-v.im, wk1.im, c.re - w.re));
       xreg[q].im = fma(-v.im, wk1.re, fma(v.re, wk1.im, c.im - w.im));
       const R t = fma(xreg[q].re, xreg[q].re, xreg[q].im * xreg[q].im);
@@ -312,7 +361,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
       update<P>(A, vk, wb);
     }
     wave_lds_fence();
-    if (k1 + 1 < n) Base::store_col(A, k1 + 1, sm.col[kb]);  // column k+2 of A^{(k+1)}
+    if (k1 + 1 < n) store_next_col<P>(A, k1 + 1, sm.col[kb]);  // column k+2 of A^{(k+1)}
     // ---- (4) y_{k+1}
     R part[2 * LR];
     product<P>(A, vn, part);
