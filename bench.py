@@ -30,11 +30,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix): 256 CU x 2.4 GHz x 128 flop/clk/CU
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk/CU
-# HBM bytes per launch of the autotuned FP64 reduction (fused, rank-2 update on MFMA) at the
-# headline workload, from the
-# FETCH_SIZE / WRITE_SIZE counters of `bench.py --counter-run` scaled by the calibration
-# transfers (FETCH_SIZE x 1.996, WRITE_SIZE x 1.0); re-measure whenever the kernel changes.
-TRAFFIC_BYTES_FP64_REDUCE = 5.06e6
+# HBM bytes per launch of the autotuned FP64 reduction (split, rank-2 update on MFMA) at the
+# headline workload, from the FETCH_SIZE / WRITE_SIZE counters of `bench.py --counter-run`
+# (574.4 + 1040.0 KiB) scaled by the calibration transfers (FETCH_SIZE x 1.996, WRITE_SIZE
+# x 1.0); re-measure whenever the kernel changes.
+TRAFFIC_BYTES_FP64_REDUCE = 2.24e6
+TRAFFIC_KERNEL = "split 32x16 grid, rank-2 update on MFMA"  # the variant those counters cover
 
 
 def reduce_flops(n):
@@ -286,6 +287,7 @@ def main():
     ff = None if a.no_full_form else full_form(tca, a, stream)
     un = None if a.no_uneven else batched_uneven(tca, stream)
 
+    chosen = report.strip().splitlines()[0].split("-> ")[-1]
     out = {
         "metric": "cluster diagonalizations & exact-equivalent MC updates/sec at 8×8 cluster; ΔF err",
         "value": value,
@@ -317,9 +319,8 @@ def main():
         "autotuner": report.strip().splitlines() + report_m.strip().splitlines(),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": TRAFFIC_BYTES_FP64_REDUCE,
-                     "kernel": "cluster_block_reduce, n=128 FP64, autotuned: "
-                               + report.strip().splitlines()[0].split("-> ")[-1],
+                     "traffic": TRAFFIC_BYTES_FP64_REDUCE if chosen == TRAFFIC_KERNEL else None,
+                     "kernel": "cluster_block_reduce, n=128 FP64, autotuned: " + chosen,
                      "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "full_form": ff,
