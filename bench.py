@@ -186,6 +186,26 @@ def full_form(tca, a, stream):
                       "untrained_rmse_bf16": untrained["holdout_rmse_bf16"],
                       "collect_and_train_s": t_train},
     }
+    # the second coupling of the workload, with the same surrogate (it predicts the
+    # fermionic dF only, which J_AF does not enter)
+    JAF2 = 0.08
+    da2 = tca.Lattice(320, Lc, seed=seed + 10, JAF=JAF2, precision=tca.TCA_MIXED, stream=stream)
+    da2.attach(sg)
+    t4 = time.perf_counter()
+    _, st2 = da2.sweep(Ts)
+    upd_da2 = st2["updates"] / (time.perf_counter() - t4)
+    da2.close()
+    plain2 = tca.Lattice(320, Lc, seed=seed + 10, JAF=JAF2, stream=stream)
+    plain2.sweep([Ts[0]])
+    t5 = time.perf_counter()
+    _, sp2 = plain2.sweep(Ts[:5])
+    upd_plain2 = sp2["updates"] / (time.perf_counter() - t5)
+    plain2.close()
+    out["jaf_0.08"] = {"updates_per_s_surrogate_mixed": upd_da2,
+                       "updates_per_s_plain_fp64": upd_plain2,
+                       "ratio_vs_plain_fp64": upd_da2 / upd_plain2,
+                       "stage1_pass_rate": st2["stage1_passed"] / st2["updates"],
+                       "accept_rate": st2["accepted"] / st2["updates"]}
     # S(q) of the two chains after the same (shortened) anneal from the same start
     if a.sq_check_sweeps > 0:
         Kq = a.sq_check_sweeps

@@ -110,55 +110,117 @@ __device__ __forceinline__ float rsqrt_nr(float s) {
 }
 
 template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false>
-struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
-  typedef ReduceFused<TR, TC, LR, LC, R, MW, MF> Base;
-  typedef typename Base::Regs Regs;
+struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
+  typedef ReduceFused<TR, TC, LR, LC, R, MW, false> Base;
   typedef typename Base::Smem Smem;
   typedef typename Base::R4 R4;
   static constexpr int NT = Base::NT;
   static constexpr int NW = Base::NW;
   static constexpr int NP = Base::NP;
   static constexpr int NQ = Base::NQ;
+  static constexpr int NLOC = Base::NLOC;
   static constexpr int RATIO = Base::RATIO;
   static constexpr int MINW = Base::MINW;
+  static constexpr int NA = LR / 4;  // MFMA row tiles per column block
   static_assert(TC == 16, "row groups of 16 lanes");
   static_assert(2 * LR <= 16, "at most 16 row values per lane");
+  static_assert(!MF || (LR % 4 == 0 && TR == 4 * NW), "matrix-core tiles need LR = 4a");
+
+  // Register storage.  With MF, the registers of column block lj and row
+  // blocks 4a .. 4a+3 of wavefront w form one MFMA 16 x 16 accumulator tile
+  // (real and imaginary parts apart): register r of lane l holds row
+  // 4w + l/16 + TR (4a + r), column 16 lj + l % 16, which is where the FP32
+  // (row 4 (l/16) + r) and the FP64 (row l/16 + 4r) accumulator layouts put
+  // tile row l/16 + 4r resp. 4 (l/16) + r.
+  struct TileRegs {
+    R4 re[LC][NA > 0 ? NA : 1], im[LC][NA > 0 ? NA : 1];
+  };
+  typedef typename std::conditional<MF, TileRegs, cx<R>[NLOC]>::type Regs;
+
+  static __device__ __forceinline__ cx<R> get(const Regs& A, int li, int lj) {
+    if constexpr (MF)
+      return {A.re[lj][li >> 2][li & 3], A.im[lj][li >> 2][li & 3]};
+    else
+      return A[li * LC + lj];
+  }
+  static __device__ __forceinline__ void set(Regs& A, int li, int lj, cx<R> v) {
+    if constexpr (MF) {
+      A.re[lj][li >> 2][li & 3] = v.re;
+      A.im[lj][li >> 2][li & 3] = v.im;
+    } else {
+      A[li * LC + lj] = v;
+    }
+  }
+  template <class F>
+  static __device__ __forceinline__ void load(Regs& A, const int n, F&& lower) {
+    const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
+#pragma unroll
+    for (int li = 0; li < LR; ++li) {
+#pragma unroll
+      for (int lj = 0; lj < LC; ++lj) {
+        const int i = tr + TR * li, j = tc + TC * lj;
+        cx<R> v = {R(0), R(0)};
+        if (i < n && j < n) {
+          if (i >= j) {
+            v = lower(i, j);
+          } else {
+            v = lower(j, i);
+            v.im = -v.im;
+          }
+        }
+        set(A, li, lj, v);
+      }
+    }
+  }
 
   // MFMA operands of the rank-2 update of phase P: row components of v and w
-  // (A operand, negated) and the column components of w and v of every
-  // active column block (B operand), read from LDS once.
+  // (A operand, negated) of every active row tile and the column components
+  // of w and v of every active column block (B operand), read from LDS once.
   struct MfOps {
-    R aop_re, aop_im;
+    R aop_re[NA > 0 ? NA : 1], aop_im[NA > 0 ? NA : 1];
     R bop[LC];
   };
   template <int P>
   static __device__ __forceinline__ MfOps mf_ops(const cx<R>* __restrict__ vk,
                                                  const cx<R>* __restrict__ wk) {
+    constexpr int A0 = (P / RATIO) / 4;
     const int tc = threadIdx.x % TC;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, ii = lane & 15;
-    const int row = sizeof(R) == 8 ? 4 * wave + (ii & 3) + 32 * (ii >> 2)
-                                   : 4 * wave + (ii >> 2) + 32 * (ii & 3);
-    const R* ra = reinterpret_cast<const R*>(g < 2 ? vk : wk) + 2 * row;
+    // tile row ii -> (group, register) -> matrix row
+    const int rg = sizeof(R) == 8 ? (ii & 3) : (ii >> 2), rr = sizeof(R) == 8 ? (ii >> 2) : (ii & 3);
     const R* rb = reinterpret_cast<const R*>(g < 2 ? wk : vk) + 2 * tc + (g & 1);
     MfOps o;
-    o.aop_re = -ra[g & 1];
-    o.aop_im = (g & 1) ? ra[0] : -ra[1];
+#pragma unroll
+    for (int a = A0; a < NA; ++a) {
+      const int row = 4 * wave + rg + TR * (4 * a + rr);
+      const R* ra = reinterpret_cast<const R*>(g < 2 ? vk : wk) + 2 * row;
+      o.aop_re[a] = -ra[g & 1];
+      o.aop_im[a] = (g & 1) ? ra[0] : -ra[1];
+    }
 #pragma unroll
     for (int lj = P; lj < LC; ++lj) o.bop[lj] = rb[2 * TC * lj];
     return o;
   }
-  // Issue the update MFMAs of column blocks J0 .. J1-1.
-  template <int J0, int J1>
+  // Issue the update MFMAs of the active tiles of phase P.
+  template <int P>
   static __device__ __forceinline__ void mf_tiles(Regs& A, const MfOps& o) {
-    static_for<J0, J1>([&](auto LJ) {
+    constexpr int A0 = (P / RATIO) / 4;
+    static_for<P, LC>([&](auto LJ) {
       constexpr int lj = decltype(LJ)::value;
-      if constexpr (sizeof(R) == 8) {
-        A.re[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.aop_re, o.bop[lj], A.re[lj], 0, 0, 0);
-        A.im[lj] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.aop_im, o.bop[lj], A.im[lj], 0, 0, 0);
-      } else {
-        A.re[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.aop_re, o.bop[lj], A.re[lj], 0, 0, 0);
-        A.im[lj] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.aop_im, o.bop[lj], A.im[lj], 0, 0, 0);
-      }
+      static_for<A0, NA>([&](auto AA) {
+        constexpr int a = decltype(AA)::value;
+        if constexpr (sizeof(R) == 8) {
+          A.re[lj][a] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(o.aop_re[a], o.bop[lj], A.re[lj][a], 0, 0, 0);
+          A.im[lj][a] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(o.aop_im[a], o.bop[lj], A.im[lj][a], 0, 0, 0);
+        } else {
+          A.re[lj][a] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(o.aop_re[a], o.bop[lj], A.re[lj][a], 0, 0, 0);
+          A.im[lj][a] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(o.aop_im[a], o.bop[lj], A.im[lj][a], 0, 0, 0);
+        }
+      });
     });
   }
 
@@ -169,7 +231,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
     constexpr int KR = P / RATIO;
     const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
     if constexpr (MF) {
-      mf_tiles<P, LC>(A, mf_ops<P>(vk, wk));
+      mf_tiles<P>(A, mf_ops<P>(vk, wk));
     } else {
       cx<R> vr[LR], wr[LR];
 #pragma unroll
@@ -183,7 +245,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
         const cx<R> vc = vk[j], wc = wk[j];
 #pragma unroll
         for (int li = KR; li < LR; ++li) {
-          cx<R> a = Base::get(A, li, lj);
+          cx<R> a = get(A, li, lj);
           a.re = fma(-vr[li].re, wc.re, a.re);
           a.re = fma(-vr[li].im, wc.im, a.re);
           a.re = fma(-wr[li].re, vc.re, a.re);
@@ -192,7 +254,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
           a.im = fma(vr[li].re, wc.im, a.im);
           a.im = fma(-wr[li].im, vc.re, a.im);
           a.im = fma(wr[li].re, vc.im, a.im);
-          Base::set(A, li, lj, a);
+          set(A, li, lj, a);
         }
       }
     }
@@ -210,7 +272,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
     if (tc == wc % TC) {
 #pragma unroll
       for (int li = 0; li < LR; ++li) {
-        const cx<R> a = Base::get(A, li, P), b = Base::get(A, li, P1);
+        const cx<R> a = get(A, li, P), b = get(A, li, P1);
         colbuf[tr + TR * li] = {in_p ? a.re : b.re, in_p ? a.im : b.im};
       }
     }
@@ -229,7 +291,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
       const cx<R> xc = x[tc + TC * lj];
 #pragma unroll
       for (int li = KR; li < LR; ++li) {
-        const cx<R> a = Base::get(A, li, lj);
+        const cx<R> a = get(A, li, lj);
         part[2 * li] = fma(a.re, xc.re, part[2 * li]);
         part[2 * li] = fma(-a.im, xc.im, part[2 * li]);
         part[2 * li + 1] = fma(a.re, xc.im, part[2 * li + 1]);
@@ -401,7 +463,13 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, MF> {
       sm.wb[wave][i] = {R(0), R(0)};
     }
     for (int i = tid; i < 2 * NP; i += NT) sm.y[i / NP][i % NP] = {R(0), R(0)};
-    Base::store_col(A, 0, sm.col[0]);
+    {
+      const int tr = tid / TC, tc = tid % TC;
+      if (tc == 0) {
+#pragma unroll
+        for (int li = 0; li < LR; ++li) sm.col[0][tr + TR * li] = get(A, li, 0);
+      }
+    }
     __syncthreads();
     R tre = R(0), tim = R(0);
     int k = -1;

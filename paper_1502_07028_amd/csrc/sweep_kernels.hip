@@ -1,5 +1,6 @@
 // Kernels of a sweep around the cluster solves:
-//  decide_kernel     Metropolis decisions of one parallel block in an order
+//  decide_kernel,
+//  decide_wave_kernel  Metropolis decisions of one parallel block in an order
 //                    equivalent to the sequential sweep (Sec. II(c) steps
 //                    (e)-(f)), committing accepted spins;
 //  classify_kernel   per-update cluster size classes of one block;
@@ -185,6 +186,144 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S, BlockGeom g, Mo
   if (threadIdx.x == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
 }
 
+// The classical term from the four neighbour spins (-x, +x, -y, +y), the
+// site's spin s and the proposal sn, in the operation order of
+// classical_delta (every operation rounded on its own).
+__device__ __forceinline__ double classical_term(const double* a, const double* b, const double* c,
+                                                 const double* d, const double* s,
+                                                 const double* sn, double JAF) {
+#pragma clang fp contract(off)
+  double acc[3], df[3];
+  for (int k = 0; k < 3; ++k) {
+    acc[k] = ((a[k] + b[k]) + c[k]) + d[k];
+    df[k] = sn[k] - s[k];
+  }
+  double dot = df[0] * acc[0];
+  dot = dot + df[1] * acc[1];
+  dot = dot + df[2] * acc[2];
+  return JAF * dot;
+}
+
+// Anti-diagonal decision pass for J_AF != 0 and blocks of side h <= 512:
+// the same decisions as decide_kernel, with the state the pass creates kept
+// on chip.  Site (i, j) of anti-diagonal d = i + j needs the final spins of
+// (i-1, j) and (i, j-1), both on anti-diagonal d-1, which the previous
+// iteration left in LDS; its own spin, the +x and +y neighbours (decided only
+// later) and neighbours outside the block still hold their block-start values
+// and, with the per-cluster record, are read from memory one anti-diagonal
+// ahead, so the global-memory latency stays off the sequential chain.
+constexpr int kWaveMaxH = 512;  // one thread per site of an anti-diagonal
+
+struct WaveSite {
+  DecidePrep pr;
+  double s[3], xm[3], xp[3], ym[3], yp[3];
+  int i, j, c, site;
+  bool valid;
+};
+
+__device__ __forceinline__ void wave_fetch(const double* S, const BlockGeom& g,
+                                           const DecidePrep* __restrict__ prep, int dd,
+                                           WaveSite& w) {
+  const int h = g.h, L = g.L;
+  const int lo = max(0, dd - (h - 1));
+  const int cnt = min(dd, h - 1) - lo + 1;
+  w.valid = (int)threadIdx.x < cnt;
+  if (!w.valid) return;
+  w.i = lo + (int)threadIdx.x;
+  w.j = dd - w.i;
+  w.c = w.i + h * w.j;
+  const int px = g.x0 + w.i, py = g.y0 + w.j;
+  w.site = px + L * py;
+  w.pr = prep[w.c];
+  const int xm = (px + L - 1) % L, xp = (px + 1) % L, ym = (py + L - 1) % L, yp = (py + 1) % L;
+  for (int k = 0; k < 3; ++k) {
+    w.s[k] = S[3 * w.site + k];
+    w.xp[k] = S[3 * (xp + L * py) + k];
+    w.yp[k] = S[3 * (px + L * yp) + k];
+    w.xm[k] = w.i == 0 ? S[3 * (xm + L * py) + k] : 0.0;
+    w.ym[k] = w.j == 0 ? S[3 * (px + L * ym) + k] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kWaveMaxH) void decide_wave_kernel(
+    double* S, BlockGeom g, ModelParams m, SweepRef sr, int K, bool da,
+    const DecidePrep* __restrict__ prep, tca_update_record* __restrict__ log_base,
+    unsigned long long* __restrict__ counters) {
+  __shared__ double fin[2][kWaveMaxH][3];  // final spins of an anti-diagonal, by row i
+  const int h = g.h, L = g.L;
+  const double T = sr.T();
+  tca_update_record* logbuf =
+      log_base != nullptr ? log_base + (size_t)sr.s() * (size_t)L * (size_t)L : nullptr;
+  unsigned long long nacc = 0, nnear = 0, npass = 0;
+  const int nd = 2 * h - 1;
+  // anti-diagonal dd from cur, while the loads of dd + 1 into nxt are in flight
+  auto diagonal = [&](const int dd, const WaveSite& cur, WaveSite& nxt) {
+    if (dd + 1 < nd) wave_fetch(S, g, prep, dd + 1, nxt);
+    if (cur.valid) {
+      const double(*prev)[3] = fin[(dd + 1) & 1];  // anti-diagonal dd - 1
+      double a[3], c[3];
+      for (int k = 0; k < 3; ++k) {
+        a[k] = cur.i > 0 ? prev[cur.i - 1][k] : cur.xm[k];
+        c[k] = cur.j > 0 ? prev[cur.i][k] : cur.ym[k];
+      }
+      const DecidePrep& pr = cur.pr;
+      const bool stage1 = (pr.flags & 2) != 0;
+      double dE = __builtin_nan("");
+      bool acc = false, near = false;
+      if (stage1) {
+        dE = pr.dF + classical_term(a, cur.xp, c, cur.yp, cur.s, pr.sn, m.JAF);
+        if (!da) {
+          acc = (dE <= 0.0) || (pr.u < exp(-dE / T));
+          if (pr.u > 0.0) near = fabs(dE + T * pr.lnu) <= 1e-9 * fmax(fabs(dE), 1e-3);
+        } else {
+          const double rhs = -dE / T + pr.sa - pr.sb;
+          acc = (pr.u <= 0.0) || (pr.lnu < rhs);
+          if (pr.u > 0.0) near = fabs(T * (pr.lnu - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+        }
+      }
+      for (int k = 0; k < 3; ++k) fin[dd & 1][cur.i][k] = acc ? pr.sn[k] : cur.s[k];
+      if (acc) {
+        S[3 * cur.site + 0] = pr.sn[0];
+        S[3 * cur.site + 1] = pr.sn[1];
+        S[3 * cur.site + 2] = pr.sn[2];
+      }
+      nacc += acc;
+      nnear += near;
+      npass += stage1;
+      if (logbuf != nullptr) {
+        tca_update_record rec;
+        rec.site = cur.site;
+        rec.Lc = pr.Lc;
+        rec.accept = acc ? 1 : 0;
+        rec.flags = (uint8_t)((near ? 1 : 0) | pr.flags);
+        rec.dF = pr.dF;
+        rec.dE = dE;
+        rec.u = pr.u;
+        rec.dS_f = pr.dSf;
+        rec.dS_r = pr.dSr;
+        logbuf[(size_t)K * h * h + cur.c] = rec;
+      }
+    }
+    // a barrier that orders the LDS only: the global loads of the next
+    // anti-diagonal stay in flight (no global location is written and read
+    // within the pass)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  };
+  // two site buffers used alternately, so no copy waits for loads in flight
+  WaveSite w0, w1;
+  wave_fetch(S, g, prep, 0, w0);
+  for (int dd = 0; dd < nd; dd += 2) {
+    diagonal(dd, w0, w1);
+    if (dd + 1 < nd) diagonal(dd + 1, w1, w0);
+  }
+  if (nacc) atomicAdd(&counters[0], nacc);
+  if (nnear) atomicAdd(&counters[1], nnear);
+  if (npass) atomicAdd(&counters[3], npass);
+  if (threadIdx.x == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
+}
+
 __global__ void classify_kernel(int4 classes, int n_classes, BlockGeom g, uint64_t seed,
                                 SweepRef sr, int32_t* __restrict__ count,
                                 int32_t* __restrict__ list) {
@@ -294,8 +433,12 @@ hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParam
   const int hh = g.h * g.h;
   hipLaunchKernelGGL(decide_prep_kernel, dim3((hh + 255) / 256), dim3(256), 0, st, Fpair, g, m, sr,
                      Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, pass, dS, prep);
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, g, m, sr, K, pass != nullptr,
-                     (const DecidePrep*)prep, log_base, counters);
+  if (m.JAF != 0.0 && g.h <= kWaveMaxH)
+    hipLaunchKernelGGL(decide_wave_kernel, dim3(1), dim3(kWaveMaxH), 0, st, S, g, m, sr, K,
+                       pass != nullptr, (const DecidePrep*)prep, log_base, counters);
+  else
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(1024), 0, st, S, g, m, sr, K, pass != nullptr,
+                       (const DecidePrep*)prep, log_base, counters);
   return hipGetLastError();
 }
 
