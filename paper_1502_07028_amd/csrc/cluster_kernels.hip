@@ -274,7 +274,8 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
                : v == 6 ? f(ReduceSplit<32, 16, 4, 8, R, 2, true>{}, R{})
                : v == 7 ? f(ReduceSplit<16, 16, 8, 8, R, 2>{}, R{})
                : v == 8 ? f(ReduceFused<16, 16, 8, 8, R, 2>{}, R{})
-                        : f(ReduceSplit<16, 16, 8, 8, R, 2, true>{}, R{});
+               : v == 9 ? f(ReduceSplit<16, 16, 8, 8, R, 2, true>{}, R{})
+                        : f(ReduceSplit<32, 8, 4, 16, R, 2>{}, R{});
       case 4:
         return v == 0   ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{})
                : v == 1 ? f(ReduceFull<32, 16, 6, 11, R>{}, R{})
@@ -309,7 +310,7 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
   return hipErrorInvalidValue;
 }
 
-constexpr int kMaxVariants = 10;
+constexpr int kMaxVariants = 11;
 static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
     {{"fused 8x8 grid", "two-pass 8x8 grid"},
      {"fused 16x16 grid", "two-pass 16x16 grid", "split 16x16 grid"},
@@ -327,7 +328,8 @@ static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
       "split 32x16 grid, 2 workgroups/CU",
       "split 32x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
       "split 16x16 grid, 2 workgroups/CU", "fused 16x16 grid, 2 workgroups/CU",
-      "split 16x16 grid, rank-2 update on MFMA, 2 workgroups/CU"},
+      "split 16x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
+      "split 32x8 grid, 2 workgroups/CU"},
      {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"},
      {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"}}};
 

@@ -66,15 +66,16 @@ __device__ __forceinline__ T wave_total_rows(T v) {
   return readlane_t(v, 63);
 }
 
-// Reduce-scatter of P values (P in 2, 4, 8, 16) over a row of 16 lanes; lane
-// l ends with the row total of value reduce_scatter_index<16, P>(l), and the
-// lanes of a duplicate group all hold it.
-template <int P, typename T>
-__device__ __forceinline__ T rs16(const T (&v)[P], const int l) {
-  static_assert(P == 2 || P == 4 || P == 8 || P == 16, "width 2, 4, 8 or 16");
-  if constexpr (P == 16 || P == 8) {
-    return reduce_scatter<16, P>(v, l);
-  } else if constexpr (P == 4) {
+// Reduce-scatter of P values (P a power of two, 2 <= P <= TC) over a row
+// group of TC = 8 or 16 lanes; lane l ends with the group total of value
+// reduce_scatter_index<TC, P>(l), and the lanes of a duplicate group all hold
+// it.
+template <int TC, int P, typename T>
+__device__ __forceinline__ T rs_group(const T (&v)[P], const int l) {
+  static_assert((TC == 8 || TC == 16) && P >= 2 && P <= TC && (P & (P - 1)) == 0, "bad width");
+  if constexpr (P == TC || (TC == 16 && P == 8)) {
+    return reduce_scatter<TC, P>(v, l);
+  } else if constexpr (TC == 16 && P == 4) {
     T a2[2], a1[1];
     rs_stage<kDppRowMirror>(v, a2, (l & 8) != 0);
     rs_stage<kDppRowHalfMirror>(a2, a1, (l & 4) != 0);
@@ -82,11 +83,25 @@ __device__ __forceinline__ T rs16(const T (&v)[P], const int l) {
     r += dpp_mov<kDppQuadReverse>(r);
     r += dpp_mov<kDppQuadSwap1>(r);
     return r;
-  } else {
+  } else if constexpr (TC == 16) {  // P == 2
     T a1[1];
     rs_stage<kDppRowMirror>(v, a1, (l & 8) != 0);
     T r = a1[0];
     r += dpp_mov<kDppRowHalfMirror>(r);
+    r += dpp_mov<kDppQuadReverse>(r);
+    r += dpp_mov<kDppQuadSwap1>(r);
+    return r;
+  } else if constexpr (P == 4) {  // TC == 8
+    T a2[2], a1[1];
+    rs_stage<kDppRowHalfMirror>(v, a2, (l & 4) != 0);
+    rs_stage<kDppQuadReverse>(a2, a1, (l & 2) != 0);
+    T r = a1[0];
+    r += dpp_mov<kDppQuadSwap1>(r);
+    return r;
+  } else {  // TC == 8, P == 2
+    T a1[1];
+    rs_stage<kDppRowHalfMirror>(v, a1, (l & 4) != 0);
+    T r = a1[0];
     r += dpp_mov<kDppQuadReverse>(r);
     r += dpp_mov<kDppQuadSwap1>(r);
     return r;
@@ -121,9 +136,10 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
   static constexpr int NLOC = Base::NLOC;
   static constexpr int RATIO = Base::RATIO;
   static constexpr int MINW = Base::MINW;
-  static constexpr int NA = LR / 4;  // MFMA row tiles per column block
-  static_assert(TC == 16, "row groups of 16 lanes");
-  static_assert(2 * LR <= 16, "at most 16 row values per lane");
+  static constexpr int NRT = LR / 4;  // MFMA row tiles per column block
+  static_assert(TC == 8 || TC == 16, "row groups of 8 or 16 lanes");
+  static_assert(2 * LR <= TC, "at most TC row values per lane");
+  static_assert(!MF || TC == 16, "matrix-core tiles need 16-lane row groups");
   static_assert(!MF || (LR % 4 == 0 && TR == 4 * NW), "matrix-core tiles need LR = 4a");
 
   // Register storage.  With MF, the registers of column block lj and row
@@ -133,7 +149,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
   // (row 4 (l/16) + r) and the FP64 (row l/16 + 4r) accumulator layouts put
   // tile row l/16 + 4r resp. 4 (l/16) + r.
   struct TileRegs {
-    R4 re[LC][NA > 0 ? NA : 1], im[LC][NA > 0 ? NA : 1];
+    R4 re[LC][NRT > 0 ? NRT : 1], im[LC][NRT > 0 ? NRT : 1];
   };
   typedef typename std::conditional<MF, TileRegs, cx<R>[NLOC]>::type Regs;
 
@@ -177,7 +193,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
   // (A operand, negated) of every active row tile and the column components
   // of w and v of every active column block (B operand), read from LDS once.
   struct MfOps {
-    R aop_re[NA > 0 ? NA : 1], aop_im[NA > 0 ? NA : 1];
+    R aop_re[NRT > 0 ? NRT : 1], aop_im[NRT > 0 ? NRT : 1];
     R bop[LC];
   };
   template <int P>
@@ -191,7 +207,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     const R* rb = reinterpret_cast<const R*>(g < 2 ? wk : vk) + 2 * tc + (g & 1);
     MfOps o;
 #pragma unroll
-    for (int a = A0; a < NA; ++a) {
+    for (int a = A0; a < NRT; ++a) {
       const int row = 4 * wave + rg + TR * (4 * a + rr);
       const R* ra = reinterpret_cast<const R*>(g < 2 ? vk : wk) + 2 * row;
       o.aop_re[a] = -ra[g & 1];
@@ -207,7 +223,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     constexpr int A0 = (P / RATIO) / 4;
     static_for<P, LC>([&](auto LJ) {
       constexpr int lj = decltype(LJ)::value;
-      static_for<A0, NA>([&](auto AA) {
+      static_for<A0, NRT>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
         if constexpr (sizeof(R) == 8) {
           A.re[lj][a] =
@@ -384,6 +400,7 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     constexpr int KR = P / RATIO;
     constexpr int NA = 2 * (LR - KR);  // row values still active
     constexpr int PA = NA <= 2 ? 2 : NA <= 4 ? 4 : NA <= 8 ? 8 : 16;
+    static_assert(PA <= TC, "row values exceed the row group");
     const int tid = threadIdx.x, tr = tid / TC, lane = tid & 63, wave = tid >> 6;
     const int lg = tid % TC;
     const int kb = k & 1, nb = (k + 1) & 1, k1 = k + 1;
@@ -430,11 +447,11 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     R pa[PA];
 #pragma unroll
     for (int q = 0; q < PA; ++q) pa[q] = q < NA ? part[2 * KR + q] : R(0);
-    const R ysum = rs16<PA>(pa, lg);
+    const R ysum = rs_group<TC, PA>(pa, lg);
     if (k1 <= n - 3) {
-      const int q = reduce_scatter_index<16, PA>(lg);
+      const int q = reduce_scatter_index<TC, PA>(lg);
       const int i = tr + TR * (KR + (q >> 1));
-      if (reduce_scatter_writer<16, PA>(lg) && q < NA && i > k1 && i < n) {
+      if (reduce_scatter_writer<TC, PA>(lg) && q < NA && i > k1 && i < n) {
         if (q & 1)
           sm.y[nb][i].im = ysum;
         else
