@@ -14,7 +14,9 @@
 //   (3) update  A^{(k+1)} = A^{(k)} - v_k w_k^H - w_k v_k^H       (registers)
 //   (4) product y_{k+1} = A^{(k+1)} v_{k+1}, row reduce-scatter, barrier.
 // (2) and (3) are independent.  With MF the update is a pair of MFMA
-// products per 16 x 16 tile, all operands read from LDS first and the MFMAs
+// products per 16 x 16 tile (but for the last VT column blocks, which the
+// vector ALUs update after (2): FP64 matrix cores and vector ALUs have the
+// same peak, so the two share the work), all operands read from LDS first and the MFMAs
 // issued before (2), so that the matrix cores work while the vector ALUs
 // build the reflector (issuing them in groups between the parts of (2),
 // pinned by scheduling barriers, measured slower); otherwise (2) runs first,
@@ -124,7 +126,7 @@ __device__ __forceinline__ float rsqrt_nr(float s) {
   return fmaf(0.5f * r, e, r);
 }
 
-template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false>
+template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false, int VT = 0>
 struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
   typedef ReduceFused<TR, TC, LR, LC, R, MW, false> Base;
   typedef typename Base::Smem Smem;
@@ -217,11 +219,12 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     for (int lj = P; lj < LC; ++lj) o.bop[lj] = rb[2 * TC * lj];
     return o;
   }
-  // Issue the update MFMAs of the active tiles of phase P.
-  template <int P>
+  // Issue the update MFMAs of the active tiles of phase P in column blocks
+  // below JE.
+  template <int P, int JE>
   static __device__ __forceinline__ void mf_tiles(Regs& A, const MfOps& o) {
     constexpr int A0 = (P / RATIO) / 4;
-    static_for<P, LC>([&](auto LJ) {
+    static_for<P, JE>([&](auto LJ) {
       constexpr int lj = decltype(LJ)::value;
       static_for<A0, NRT>([&](auto AA) {
         constexpr int a = decltype(AA)::value;
@@ -240,38 +243,34 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     });
   }
 
-  // A <- A - vk wk^H - wk vk^H on the blocks of phase P.
-  template <int P>
-  static __device__ __forceinline__ void update(Regs& A, const cx<R>* __restrict__ vk,
-                                                const cx<R>* __restrict__ wk) {
-    constexpr int KR = P / RATIO;
+  // A <- A - vk wk^H - wk vk^H on the vector ALUs, row blocks from KR and
+  // column blocks from J0.
+  template <int KR, int J0>
+  static __device__ __forceinline__ void valu_update(Regs& A, const cx<R>* __restrict__ vk,
+                                                     const cx<R>* __restrict__ wk) {
     const int tr = threadIdx.x / TC, tc = threadIdx.x % TC;
-    if constexpr (MF) {
-      mf_tiles<P>(A, mf_ops<P>(vk, wk));
-    } else {
-      cx<R> vr[LR], wr[LR];
+    cx<R> vr[LR], wr[LR];
+#pragma unroll
+    for (int li = KR; li < LR; ++li) {
+      vr[li] = vk[tr + TR * li];
+      wr[li] = wk[tr + TR * li];
+    }
+#pragma unroll
+    for (int lj = J0; lj < LC; ++lj) {
+      const int j = tc + TC * lj;
+      const cx<R> vc = vk[j], wc = wk[j];
 #pragma unroll
       for (int li = KR; li < LR; ++li) {
-        vr[li] = vk[tr + TR * li];
-        wr[li] = wk[tr + TR * li];
-      }
-#pragma unroll
-      for (int lj = P; lj < LC; ++lj) {
-        const int j = tc + TC * lj;
-        const cx<R> vc = vk[j], wc = wk[j];
-#pragma unroll
-        for (int li = KR; li < LR; ++li) {
-          cx<R> a = get(A, li, lj);
-          a.re = fma(-vr[li].re, wc.re, a.re);
-          a.re = fma(-vr[li].im, wc.im, a.re);
-          a.re = fma(-wr[li].re, vc.re, a.re);
-          a.re = fma(-wr[li].im, vc.im, a.re);
-          a.im = fma(-vr[li].im, wc.re, a.im);
-          a.im = fma(vr[li].re, wc.im, a.im);
-          a.im = fma(-wr[li].im, vc.re, a.im);
-          a.im = fma(wr[li].re, vc.im, a.im);
-          set(A, li, lj, a);
-        }
+        cx<R> a = get(A, li, lj);
+        a.re = fma(-vr[li].re, wc.re, a.re);
+        a.re = fma(-vr[li].im, wc.im, a.re);
+        a.re = fma(-wr[li].re, vc.re, a.re);
+        a.re = fma(-wr[li].im, vc.im, a.re);
+        a.im = fma(-vr[li].im, wc.re, a.im);
+        a.im = fma(vr[li].re, wc.im, a.im);
+        a.im = fma(-wr[li].im, vc.re, a.im);
+        a.im = fma(wr[li].re, vc.im, a.im);
+        set(A, li, lj, a);
       }
     }
   }
@@ -433,11 +432,14 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     wave_lds_fence();
     // ---- (2) reflector and (3) update
     if constexpr (MF) {
-      update<P>(A, vk, wb);
+      // the last VT column blocks of the update on the vector ALUs, after (2)
+      constexpr int JE = LC - VT > P ? LC - VT : P;
+      mf_tiles<P, JE>(A, mf_ops<P>(vk, wb));
       reflect(n, k, sm, a2, tre, tim);
+      if constexpr (JE < LC) valu_update<P / RATIO, JE>(A, vk, wb);
     } else {
       reflect(n, k, sm, a2, tre, tim);
-      update<P>(A, vk, wb);
+      valu_update<P / RATIO, P>(A, vk, wb);
     }
     wave_lds_fence();
     if (k1 + 1 < n) store_next_col<P>(A, k1 + 1, sm.col[kb]);  // column k+2 of A^{(k+1)}
