@@ -303,7 +303,9 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
                : v == 2 ? f(ReduceFused<32, 16, 4, 8, R, 0, true>{}, R{})
                : v == 3 ? f(ReduceSplit<32, 16, 4, 8, R>{}, R{})
                : v == 4 ? f(ReduceSplit<32, 16, 4, 8, R, 0, true>{}, R{})
-                        : f(ReduceSplit<32, 16, 4, 8, R, 0, true, 3>{}, R{});
+               : v == 5 ? f(ReduceSplit<32, 16, 4, 8, R, 0, true, 3>{}, R{})
+               : v == 6 ? f(ReduceSplit<32, 16, 4, 8, R, 0, true, 0, true>{}, R{})
+                        : f(ReduceSplit<32, 16, 4, 8, R, 0, false, 0, true>{}, R{});
       case 4: return f(ReduceLower<16, 11, R>{}, R{});
       case 5: return f(ReduceLower<16, 13, R>{}, R{});
     }
@@ -318,7 +320,9 @@ static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
      {"fused 16x16 grid", "two-pass 16x16 grid", "split 16x16 grid"},
      {"fused 32x16 grid", "two-pass 32x16 grid", "fused 32x16 grid, rank-2 update on MFMA",
       "split 32x16 grid", "split 32x16 grid, rank-2 update on MFMA",
-      "split 32x16 grid, rank-2 update on MFMA and vector ALUs"},
+      "split 32x16 grid, rank-2 update on MFMA and vector ALUs",
+      "split 32x16 grid, rank-2 update on MFMA, reflector on half the wavefronts",
+      "split 32x16 grid, reflector on half the wavefronts"},
      {"lower-triangle 16x16 grid"},
      {"lower-triangle 16x16 grid"}},
     {{"fused 8x8 grid", "two-pass 8x8 grid"},

@@ -22,6 +22,10 @@
 // pinned by scheduling barriers, measured slower); otherwise (2) runs first,
 // which keeps the register update and the product together.
 //
+// With LD, only the lower half of the wavefronts (one per SIMD) builds the
+// reflector; the other half issues its update and waits at a second barrier,
+// then takes v_{k+1} and tau from the leaders' LDS copies.
+//
 // Less vector work per step.
 //  - Buffers are cleared once, so v_k vanishes outside rows k+1..n-1 and y_k
 //    is finite everywhere: c needs no row mask, and w_k may hold nonzero
@@ -126,10 +130,13 @@ __device__ __forceinline__ float rsqrt_nr(float s) {
   return fmaf(0.5f * r, e, r);
 }
 
-template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false, int VT = 0>
+template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false, int VT = 0,
+          bool LD = false>
 struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
   typedef ReduceFused<TR, TC, LR, LC, R, MW, false> Base;
-  typedef typename Base::Smem Smem;
+  struct Smem : Base::Smem {
+    R tau[2][2];  // tau of the newest reflector (by step parity), for the followers
+  };
   typedef typename Base::R4 R4;
   static constexpr int NT = Base::NT;
   static constexpr int NW = Base::NW;
@@ -400,11 +407,18 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     constexpr int NA = 2 * (LR - KR);  // row values still active
     constexpr int PA = NA <= 2 ? 2 : NA <= 4 ? 4 : NA <= 8 ? 8 : 16;
     static_assert(PA <= TC, "row values exceed the row group");
-    const int tid = threadIdx.x, tr = tid / TC, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, tr = tid / TC, lane = tid & 63;
+    // with LD the wavefront index is made scalar, so the role test is a
+    // uniform branch
+    const int wave = LD ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
     const int lg = tid % TC;
     const int kb = k & 1, nb = (k + 1) & 1, k1 = k + 1;
-    const cx<R>* vk = sm.vb[wave][kb];
-    const cx<R>* vn = sm.vb[wave][nb];
+    // with LD the lower half of the wavefronts (one per SIMD) builds the
+    // reflector and the upper half uses their copies
+    const bool leader = !LD || wave < NW / 2;
+    const int lead = LD ? wave % (NW / 2) : wave;
+    const cx<R>* vk = sm.vb[lead][kb];
+    const cx<R>* vn = sm.vb[lead][nb];
     cx<R>* wb = sm.wb[wave];
     const cx<R>* yk = sm.y[kb];
     // ---- (1) w_k
@@ -431,17 +445,36 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     }
     wave_lds_fence();
     // ---- (2) reflector and (3) update
-    if constexpr (MF) {
+    if constexpr (LD) {
+      // followers: the update only, while the leaders build the reflector
+      if constexpr (MF) {
+        mf_tiles<P, LC>(A, mf_ops<P>(vk, wb));
+        if (leader) reflect(n, k, sm, a2, tre, tim);
+      } else {
+        if (leader) reflect(n, k, sm, a2, tre, tim);
+        valu_update<P / RATIO, P>(A, vk, wb);
+      }
+      if (tid == 0) {
+        sm.tau[nb][0] = tre;
+        sm.tau[nb][1] = tim;
+      }
+      __syncthreads();
+      if (!leader) {
+        tre = sm.tau[nb][0];
+        tim = sm.tau[nb][1];
+      }
+    } else if constexpr (MF) {
       // the last VT column blocks of the update on the vector ALUs, after (2)
       constexpr int JE = LC - VT > P ? LC - VT : P;
       mf_tiles<P, JE>(A, mf_ops<P>(vk, wb));
       reflect(n, k, sm, a2, tre, tim);
       if constexpr (JE < LC) valu_update<P / RATIO, JE>(A, vk, wb);
+      wave_lds_fence();
     } else {
       reflect(n, k, sm, a2, tre, tim);
       valu_update<P / RATIO, P>(A, vk, wb);
+      wave_lds_fence();
     }
-    wave_lds_fence();
     if (k1 + 1 < n) store_next_col<P>(A, k1 + 1, sm.col[kb]);  // column k+2 of A^{(k+1)}
     // ---- (4) y_{k+1}
     R part[2 * LR];

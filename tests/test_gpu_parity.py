@@ -376,7 +376,7 @@ def test_every_reducer_variant_cluster_matrices(lib, Lc, precision):
         lib.tca_select_reducer_variant(n, precision, 0)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_reducer_variants_lockstep_8x8_cluster(lib, variant):
     """Sampled lockstep replay of a 32x32 / 8x8 sweep with each FP64 reducer variant."""
     names = lib.tca_reducer_variants(128, 0)
