@@ -30,12 +30,20 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix): 256 CU x 2.4 GHz x 128 flop/clk/CU
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk/CU
-# HBM bytes per launch of the autotuned FP64 reduction (split, rank-2 update on MFMA) at the
-# headline workload, from the FETCH_SIZE / WRITE_SIZE counters of `bench.py --counter-run`
-# (574.4 + 1040.0 KiB) scaled by the calibration transfers (FETCH_SIZE x 1.996, WRITE_SIZE
-# x 1.0); re-measure whenever the kernel changes.
-TRAFFIC_BYTES_FP64_REDUCE = 2.24e6
-TRAFFIC_KERNEL = "split 32x16 grid, rank-2 update on MFMA"  # the variant those counters cover
+# HBM bytes per launch of each FP64 reduction variant the autotuner may pick at the headline
+# workload, from the FETCH_SIZE / WRITE_SIZE counters of `bench.py --counter-run` (every
+# variant runs there) scaled by the calibration transfers (FETCH_SIZE x 1.996, WRITE_SIZE x
+# 1.0); re-measure whenever a kernel changes.
+TRAFFIC_BYTES_FP64_REDUCE = {
+    "fused 32x16 grid": 2.468e6,
+    "two-pass 32x16 grid": 2.025e6,
+    "fused 32x16 grid, rank-2 update on MFMA": 5.049e6,
+    "split 32x16 grid": 2.335e6,
+    "split 32x16 grid, rank-2 update on MFMA": 2.242e6,
+    "split 32x16 grid, rank-2 update on MFMA and vector ALUs": 2.300e6,
+    "split 32x16 grid, rank-2 update on MFMA, reflector on half the wavefronts": 2.255e6,
+    "split 32x16 grid, reflector on half the wavefronts": 2.341e6,
+}
 
 
 def reduce_flops(n):
@@ -339,7 +347,7 @@ def main():
         "autotuner": report.strip().splitlines() + report_m.strip().splitlines(),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": TRAFFIC_BYTES_FP64_REDUCE if chosen == TRAFFIC_KERNEL else None,
+                     "traffic": TRAFFIC_BYTES_FP64_REDUCE.get(chosen),
                      "kernel": "cluster_block_reduce, n=128 FP64, autotuned: " + chosen,
                      "flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
