@@ -268,6 +268,8 @@ __device__ __forceinline__ int sturm_newton_pairs(const int n, const double x, c
   return (int)c;
 }
 
+constexpr double kNewtonLastStep = 2.25e6;  // ~1e-9 / (2 eps)
+
 // Eigenvalue j of T from a bracket [a, b] with counts ca <= j < cb.
 __device__ inline double tri_eigenvalue_pairs(const int n, const int j, const double2* de,
                                               double a, double b, int ca, int cb,
@@ -301,6 +303,10 @@ __device__ inline double tri_eigenvalue_pairs(const int n, const int j, const do
     const bool inside = xn > a && xn < b;
     const double st = fabs(step);
     if (st <= tol) return xn;
+    // near a simple root the error after a Newton step of size st is of order
+    // st^2 / (root spacing): a step below ~1e-9 of the spectral scale (tol is
+    // 2 eps of it) leaves an error far below tol, so it is the last one
+    if (inside && st <= kNewtonLastStep * tol) return xn;
     if (st <= 1e5 * tol && (st > 0.5 * last || !inside)) return x;
     if (!inside) xn = 0.5 * (a + b);
     last = inside ? st : b - a;
