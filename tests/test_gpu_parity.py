@@ -242,6 +242,18 @@ def test_sweep_large_lattice_sampled(lib):
     assert stats["bad"] == 0 and stats["max_rel"] <= REL_TOL
 
 
+def test_sweep_wide_block_decisions(lib):
+    """Blocks wider than 512 sites (1028x1028 lattice, 2x2 cluster, J_AF != 0)
+    take the decision kernel that reads every neighbour from memory: one sweep,
+    every decision replayed by the oracle from the logged dF, a few dF recomputed."""
+    L = 1028
+    rng = np.random.default_rng(4)
+    check = set(rng.choice(L * L, 8, replace=False).tolist())
+    res = run_lockstep(lib, L, 2, 0.05, 23, 0.1, 1, check=check)
+    recs, stats, st = res[0]
+    assert stats["bad"] == 0 and stats["max_rel"] <= REL_TOL
+
+
 def test_zero_sweeps_is_noop(lib):
     lat = lib.Lattice(8, 4, seed=1)
     S0 = lat.spins()
