@@ -279,11 +279,13 @@ static hipError_t dispatch_variant(int cls, int precision, int v, F&& f) {
       case 4:
         return v == 0   ? f(ReduceFused<32, 16, 6, 11, R, 2>{}, R{})
                : v == 1 ? f(ReduceFull<32, 16, 6, 11, R>{}, R{})
-                        : f(ReduceLower<32, 6, R>{}, R{});
+               : v == 2 ? f(ReduceLower<32, 6, R>{}, R{})
+                        : f(ReduceSplit<32, 16, 6, 11, R, 2>{}, R{});
       case 5:
         return v == 0   ? f(ReduceFused<32, 16, 7, 13, R, 2>{}, R{})
                : v == 1 ? f(ReduceFull<32, 16, 7, 13, R>{}, R{})
-                        : f(ReduceLower<32, 7, R>{}, R{});
+               : v == 2 ? f(ReduceLower<32, 7, R>{}, R{})
+                        : f(ReduceSplit<32, 16, 7, 13, R, 2>{}, R{});
     }
   } else {
     using R = double;
@@ -336,8 +338,8 @@ static const char* const kVariantNames[2][kNumReducerClasses][kMaxVariants] = {
       "split 16x16 grid, 2 workgroups/CU", "fused 16x16 grid, 2 workgroups/CU",
       "split 16x16 grid, rank-2 update on MFMA, 2 workgroups/CU",
       "split 32x8 grid, 2 workgroups/CU"},
-     {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"},
-     {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid"}}};
+     {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid", "split 32x16 grid"},
+     {"fused 32x16 grid", "two-pass 32x16 grid", "lower-triangle 32x32 grid", "split 32x16 grid"}}};
 
 static std::atomic<int> g_choice[2][kNumReducerClasses];
 
