@@ -130,6 +130,85 @@ __device__ __forceinline__ float rsqrt_nr(float s) {
   return fmaf(0.5f * r, e, r);
 }
 
+// Column k+1 of A^{(k+1)}, d_{k+1}, e_{k+1}^2, reflector k+1 into vn and
+// (tre, tim).  v_k and w_k are read back from this wavefront's LDS copies,
+// so nothing but (tau_k, a2) stays live across the register update.
+template <int NP, int NQ, typename R, class Smem>
+__device__ __forceinline__ void split_reflect(const int n, const int k, Smem& sm, const R a2, R& tre,
+                                            R& tim) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, k1 = k + 1;
+  const cx<R>* colk = sm.col[(k + 1) & 1];
+  const cx<R>* vk = sm.vb[wave][k & 1];
+  const cx<R>* wb = sm.wb[wave];
+  const cx<R>* yk = sm.y[k & 1];
+  cx<R>* vn = sm.vb[wave][(k + 1) & 1];
+  const cx<R> c1 = colk[k1], c2 = colk[k1 + 1];
+  const cx<R> y1 = yk[k1], y2 = yk[k1 + 1], v2 = vk[k1 + 1];
+  // w_k[k+1] (v_k[k+1] = 1 whenever tau_k != 0) and w_k[k+2]
+  const cx<R> wk1 = {fma(tre, y1.re, fma(-tim, y1.im, -a2)), fma(tre, y1.im, tim * y1.re)};
+  const cx<R> wk2 = {fma(tre, y2.re, fma(-tim, y2.im, -a2 * v2.re)),
+                     fma(tre, y2.im, fma(tim, y2.re, -a2 * v2.im))};
+  cx<R> cv[NQ], vv[NQ], wv[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    const int ic = i < NP ? i : NP - 1;
+    cv[q] = colk[ic];
+    vv[q] = vk[ic];
+    wv[q] = wb[ic];
+  }
+  // x_i = col_i - v_k[i] conj(w_k[k+1]) - w_k[i]
+  cx<R> xreg[NQ];
+  R s2 = R(0);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    const cx<R> c = cv[q], v = vv[q], w = wv[q];
+    xreg[q].re = fma(-v.re, wk1.re, fma(-v.im, wk1.im, c.re - w.re));
+    xreg[q].im = fma(-v.im, wk1.re, fma(v.re, wk1.im, c.im - w.im));
+    const R t = fma(xreg[q].re, xreg[q].re, xreg[q].im * xreg[q].im);
+    s2 += (i > k1 + 1 && i < n) ? t : R(0);
+  }
+  // x[k+1] (v_k[k+1] = 1 or w_k = 0) and x[k+2]
+  const R d1 = fma(R(-2), wk1.re, c1.re);
+  cx<R> al;
+  al.re = fma(-v2.re, wk1.re, fma(-v2.im, wk1.im, c2.re - wk2.re));
+  al.im = fma(-v2.im, wk1.re, fma(v2.re, wk1.im, c2.im - wk2.im));
+  s2 = wave_total_rows(s2);
+  if (tid == 0) sm.d[k1] = (double)d1;
+  const bool refl = (k1 <= n - 3);
+  const bool triv = (s2 == R(0) && al.im == R(0));
+  const bool act = refl && !triv;
+  const R s = act ? fma(al.re, al.re, fma(al.im, al.im, s2)) : R(1);
+  const R r = rsqrt_nr(s);
+  const R nrm = s * r;
+  const R sg = al.re >= R(0) ? R(1) : R(-1);
+  const R are = fabs(al.re);
+  const R dr = are + nrm;
+  const R rden = fast_rcp(fma(dr, dr, al.im * al.im));
+  const R scr = act ? sg * dr * rden : R(0);
+  const R sci = act ? -al.im * rden : R(0);
+  tre = act ? fma(are, r, R(1)) : R(0);
+  tim = act ? sg * al.im * r : R(0);
+  if (tid == 0) {
+    if (refl) {
+      const double beta = act ? -(double)sg * (double)nrm : (double)al.re;
+      sm.e2[k1] = beta * beta;
+    } else if (k1 == n - 2) {
+      sm.e2[k1] = (double)al.re * (double)al.re + (double)al.im * (double)al.im;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    const cx<R> x = xreg[q];
+    const R sr_ = fma(x.re, scr, -x.im * sci), si_ = fma(x.re, sci, x.im * scr);
+    const bool head = refl && i == k1 + 1, tail = refl && i > k1 + 1 && i < n;
+    const cx<R> v = {head ? R(1) : (tail ? sr_ : R(0)), tail ? si_ : R(0)};
+    if (NP % 64 == 0 || i < NP) vn[i] = v;
+  }
+}
+
 template <int TR, int TC, int LR, int LC, typename R, int MW = 0, bool MF = false, int VT = 0,
           bool LD = false>
 struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
@@ -322,82 +401,9 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     }
   }
 
-  // Column k+1 of A^{(k+1)}, d_{k+1}, e_{k+1}^2, reflector k+1 into vn and
-  // (tre, tim).  v_k and w_k are read back from this wavefront's LDS copies,
-  // so nothing but (tau_k, a2) stays live across the register update.
   static __device__ __forceinline__ void reflect(const int n, const int k, Smem& sm, const R a2,
                                                  R& tre, R& tim) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, k1 = k + 1;
-    const cx<R>* colk = sm.col[(k + 1) & 1];
-    const cx<R>* vk = sm.vb[wave][k & 1];
-    const cx<R>* wb = sm.wb[wave];
-    const cx<R>* yk = sm.y[k & 1];
-    cx<R>* vn = sm.vb[wave][(k + 1) & 1];
-    const cx<R> c1 = colk[k1], c2 = colk[k1 + 1];
-    const cx<R> y1 = yk[k1], y2 = yk[k1 + 1], v2 = vk[k1 + 1];
-    // w_k[k+1] (v_k[k+1] = 1 whenever tau_k != 0) and w_k[k+2]
-    const cx<R> wk1 = {fma(tre, y1.re, fma(-tim, y1.im, -a2)), fma(tre, y1.im, tim * y1.re)};
-    const cx<R> wk2 = {fma(tre, y2.re, fma(-tim, y2.im, -a2 * v2.re)),
-                       fma(tre, y2.im, fma(tim, y2.re, -a2 * v2.im))};
-    cx<R> cv[NQ], vv[NQ], wv[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
-      const int ic = i < NP ? i : NP - 1;
-      cv[q] = colk[ic];
-      vv[q] = vk[ic];
-      wv[q] = wb[ic];
-    }
-    // x_i = col_i - v_k[i] conj(w_k[k+1]) - w_k[i]
-    cx<R> xreg[NQ];
-    R s2 = R(0);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
-      const cx<R> c = cv[q], v = vv[q], w = wv[q];
-      xreg[q].re = fma(-v.re, wk1.re, fma(-v.im, wk1.im, c.re - w.re));
-      xreg[q].im = fma(-v.im, wk1.re, fma(v.re, wk1.im, c.im - w.im));
-      const R t = fma(xreg[q].re, xreg[q].re, xreg[q].im * xreg[q].im);
-      s2 += (i > k1 + 1 && i < n) ? t : R(0);
-    }
-    // x[k+1] (v_k[k+1] = 1 or w_k = 0) and x[k+2]
-    const R d1 = fma(R(-2), wk1.re, c1.re);
-    cx<R> al;
-    al.re = fma(-v2.re, wk1.re, fma(-v2.im, wk1.im, c2.re - wk2.re));
-    al.im = fma(-v2.im, wk1.re, fma(v2.re, wk1.im, c2.im - wk2.im));
-    s2 = wave_total_rows(s2);
-    if (tid == 0) sm.d[k1] = (double)d1;
-    const bool refl = (k1 <= n - 3);
-    const bool triv = (s2 == R(0) && al.im == R(0));
-    const bool act = refl && !triv;
-    const R s = act ? fma(al.re, al.re, fma(al.im, al.im, s2)) : R(1);
-    const R r = rsqrt_nr(s);
-    const R nrm = s * r;
-    const R sg = al.re >= R(0) ? R(1) : R(-1);
-    const R are = fabs(al.re);
-    const R dr = are + nrm;
-    const R rden = fast_rcp(fma(dr, dr, al.im * al.im));
-    const R scr = act ? sg * dr * rden : R(0);
-    const R sci = act ? -al.im * rden : R(0);
-    tre = act ? fma(are, r, R(1)) : R(0);
-    tim = act ? sg * al.im * r : R(0);
-    if (tid == 0) {
-      if (refl) {
-        const double beta = act ? -(double)sg * (double)nrm : (double)al.re;
-        sm.e2[k1] = beta * beta;
-      } else if (k1 == n - 2) {
-        sm.e2[k1] = (double)al.re * (double)al.re + (double)al.im * (double)al.im;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int i = lane + 64 * q;
-      const cx<R> x = xreg[q];
-      const R sr_ = fma(x.re, scr, -x.im * sci), si_ = fma(x.re, sci, x.im * scr);
-      const bool head = refl && i == k1 + 1, tail = refl && i > k1 + 1 && i < n;
-      const cx<R> v = {head ? R(1) : (tail ? sr_ : R(0)), tail ? si_ : R(0)};
-      if (NP % 64 == 0 || i < NP) vn[i] = v;
-    }
+    split_reflect<NP, NQ>(n, k, sm, a2, tre, tim);
   }
 
   template <int P>
@@ -432,7 +438,11 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     }
     R c = R(0);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) c += fma(vv[q].re, yv[q].re, vv[q].im * yv[q].im);
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      const R t = fma(vv[q].re, yv[q].re, vv[q].im * yv[q].im);
+      c += (NP % 64 == 0 || i < NP) ? t : R(0);  // lanes past NP read row NP-1 again
+    }
     c = wave_total_rows(c);
     const R a2 = R(0.5) * (tre * tre + tim * tim) * c;
 #pragma unroll

@@ -331,7 +331,7 @@ def test_autotuner_reports_choices(lib):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("n", [32, 50, 72, 128, 162, 200])
+@pytest.mark.parametrize("n", [32, 50, 72, 80, 128, 162, 200])
 def test_every_reducer_variant(lib, n, precision):
     """Each reducer variant the autotuner may pick gives the LAPACK spectrum
     (FP64 to 1e-12 of the spectral scale, mixed to the FP32 bound), on random
