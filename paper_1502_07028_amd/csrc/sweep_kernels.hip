@@ -115,18 +115,72 @@ __global__ __launch_bounds__(256) void decide_prep_kernel(const double* __restri
   prep[c] = q;
 }
 
+// Metropolis decision from the energy change dE of a stage-1 survivor.
+// Plain chain: accept iff dE <= 0 or u < exp(-dE/T).  Delayed acceptance:
+// accept iff ln u < -dE/T + sa - sb (the second-stage ratio).  Away from the
+// threshold the decision is taken from ln u against -dE * (1/T): the two sides
+// then differ by far more than the rounding of the logarithm, the exponential
+// and the quotient, so the result is the one of the exact form, which is
+// evaluated only within a relative 1e-10 of the threshold.
+constexpr double kDecideGap = 1e-10;
+
+__device__ __forceinline__ bool metropolis_accept(const double u, const double lnu,
+                                                  const double sa, const double sb,
+                                                  const double dE, const double T,
+                                                  const double invT, const bool da) {
+  if (!da) {
+    if (dE <= 0.0) return true;
+    if (!(u > 0.0)) return u < exp(-dE / T);
+    const double z = -dE * invT;
+    const double gap = lnu - z, tol = kDecideGap * (1.0 + fabs(z));
+    return gap < -tol ? true : (gap > tol ? false : u < exp(-dE / T));
+  }
+  if (u <= 0.0) return true;
+  const double z = fma(-dE, invT, sa - sb);
+  const double gap = lnu - z;
+  const double tol = kDecideGap * (1.0 + fabs(dE * invT) + fabs(sa) + fabs(sb));
+  return gap < -tol ? true : (gap > tol ? false : lnu < -dE / T + sa - sb);
+}
+
+// Near-threshold flag: |T ln u + dE| (delayed acceptance: T |ln u - rhs|)
+// below 1e-9 of max(|dE|, 1e-3).
+__device__ __forceinline__ bool metropolis_near(const double u, const double lnu,
+                                                const double sa, const double sb,
+                                                const double dE, const double T,
+                                                const bool da) {
+  if (!(u > 0.0)) return false;
+  if (!da) return fabs(dE + T * lnu) <= 1e-9 * fmax(fabs(dE), 1e-3);
+  const double rhs = -dE / T + sa - sb;
+  return fabs(T * (lnu - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
+}
+
+__device__ __forceinline__ bool metropolis_decide(const DecidePrep& pr, const double dE,
+                                                  const double T, const double invT,
+                                                  const bool da, bool& near) {
+  near = metropolis_near(pr.u, pr.lnu, pr.sa, pr.sb, dE, T, da);
+  return metropolis_accept(pr.u, pr.lnu, pr.sa, pr.sb, dE, T, invT, da);
+}
+
+// Adds the wavefront total of a per-thread count to *p with one atomic from
+// lane 0 (every lane of the wavefront takes part).
+__device__ __forceinline__ void add_wave_total(unsigned long long* p, unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v != 0u) atomicAdd(p, (unsigned long long)v);
+}
+
 __global__ __launch_bounds__(1024) void decide_kernel(double* S, BlockGeom g, ModelParams m,
                                                       SweepRef sr, int K, bool da,
                                                       const DecidePrep* __restrict__ prep,
                                                       tca_update_record* __restrict__ log_base,
                                                       unsigned long long* __restrict__ counters) {
   const int h = g.h, L = g.L;
-  const double T = sr.T();
+  const double T = sr.T(), invT = 1.0 / T;
   tca_update_record* logbuf =
       log_base != nullptr ? log_base + (size_t)sr.s() * (size_t)L * (size_t)L : nullptr;
   const bool wave = (m.JAF != 0.0);
   const int ndiag = wave ? 2 * h - 1 : 1;
-  unsigned long long nacc = 0, nnear = 0, npass = 0;
+  unsigned nacc = 0, nnear = 0, npass = 0;
   for (int dd = 0; dd < ndiag; ++dd) {
     const int lo = wave ? max(0, dd - (h - 1)) : 0;
     const int cnt = wave ? (min(dd, h - 1) - lo + 1) : h * h;
@@ -147,14 +201,7 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S, BlockGeom g, Mo
       bool acc = false, near = false;
       if (stage1) {
         dE = pr.dF + classical_delta(S, L, px, py, pr.sn, m.JAF);
-        if (!da) {
-          acc = (dE <= 0.0) || (pr.u < exp(-dE / T));
-          if (pr.u > 0.0) near = fabs(dE + T * pr.lnu) <= 1e-9 * fmax(fabs(dE), 1e-3);
-        } else {
-          const double rhs = -dE / T + pr.sa - pr.sb;
-          acc = (pr.u <= 0.0) || (pr.lnu < rhs);
-          if (pr.u > 0.0) near = fabs(T * (pr.lnu - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
-        }
+        acc = metropolis_decide(pr, dE, T, invT, da, near);
         if (acc) {
           S[3 * site + 0] = pr.sn[0];
           S[3 * site + 1] = pr.sn[1];
@@ -180,9 +227,9 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S, BlockGeom g, Mo
     }
     if (wave) __syncthreads();
   }
-  if (nacc) atomicAdd(&counters[0], nacc);
-  if (nnear) atomicAdd(&counters[1], nnear);
-  if (npass) atomicAdd(&counters[3], npass);
+  add_wave_total(&counters[0], nacc);
+  add_wave_total(&counters[1], nnear);
+  add_wave_total(&counters[3], npass);
   if (threadIdx.x == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
 }
 
@@ -251,10 +298,10 @@ __global__ __launch_bounds__(kWaveMaxH) void decide_wave_kernel(
     unsigned long long* __restrict__ counters) {
   __shared__ double fin[2][kWaveMaxH][3];  // final spins of an anti-diagonal, by row i
   const int h = g.h, L = g.L;
-  const double T = sr.T();
+  const double T = sr.T(), invT = 1.0 / T;
   tca_update_record* logbuf =
       log_base != nullptr ? log_base + (size_t)sr.s() * (size_t)L * (size_t)L : nullptr;
-  unsigned long long nacc = 0, nnear = 0, npass = 0;
+  unsigned nacc = 0, nnear = 0, npass = 0;
   const int nd = 2 * h - 1;
   // anti-diagonal dd from cur, while the loads of dd + 1 into nxt are in flight
   auto diagonal = [&](const int dd, const WaveSite& cur, WaveSite& nxt) {
@@ -272,14 +319,7 @@ __global__ __launch_bounds__(kWaveMaxH) void decide_wave_kernel(
       bool acc = false, near = false;
       if (stage1) {
         dE = pr.dF + classical_term(a, cur.xp, c, cur.yp, cur.s, pr.sn, m.JAF);
-        if (!da) {
-          acc = (dE <= 0.0) || (pr.u < exp(-dE / T));
-          if (pr.u > 0.0) near = fabs(dE + T * pr.lnu) <= 1e-9 * fmax(fabs(dE), 1e-3);
-        } else {
-          const double rhs = -dE / T + pr.sa - pr.sb;
-          acc = (pr.u <= 0.0) || (pr.lnu < rhs);
-          if (pr.u > 0.0) near = fabs(T * (pr.lnu - rhs)) <= 1e-9 * fmax(fabs(dE), 1e-3);
-        }
+        acc = metropolis_decide(pr, dE, T, invT, da, near);
       }
       for (int k = 0; k < 3; ++k) fin[dd & 1][cur.i][k] = acc ? pr.sn[k] : cur.s[k];
       if (acc) {
@@ -318,10 +358,181 @@ __global__ __launch_bounds__(kWaveMaxH) void decide_wave_kernel(
     diagonal(dd, w0, w1);
     if (dd + 1 < nd) diagonal(dd + 1, w1, w0);
   }
-  if (nacc) atomicAdd(&counters[0], nacc);
-  if (nnear) atomicAdd(&counters[1], nnear);
-  if (npass) atomicAdd(&counters[3], npass);
+  add_wave_total(&counters[0], nacc);
+  add_wave_total(&counters[1], nnear);
+  add_wave_total(&counters[3], npass);
   if (threadIdx.x == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
+}
+
+// The same pass for blocks of side h <= kStageMaxH, by one wavefront with the
+// whole block staged in LDS first: the per-cluster records and the spins of
+// the block and its one-site frame, (h + 2)^2 sites read once with every load
+// in flight together.  The staged spins are then the state of the pass: site
+// (i, j) sits at frame position (i + 1, j + 1), its decision overwrites it, and
+// its four neighbours are read from the frame, where the -x and -y ones (or
+// the frame's fixed edge) already hold their final values and the +x and +y
+// ones still hold their block-start values, which is the order of the
+// sequential sweep.  The sequential loop carries only what the next
+// anti-diagonal needs (the operands of anti-diagonal d + 1 that the pass does
+// not change are read while d is decided); decisions and dE go to LDS, and the
+// spin writes, flags, records and counters follow in a parallel pass over the
+// block.  No global memory is read after the staging.
+constexpr int kStageMaxH = 24;  // 72 h^2 + 24 (h + 2)^2 + 9 h^2 bytes of LDS <= 62 KB
+
+static size_t decide_stage_lds_bytes(int h) {
+  const size_t hh = (size_t)h * h, hf2 = (size_t)(h + 2) * (h + 2);
+  return sizeof(DecidePrep) * hh + 3 * sizeof(double) * hf2 + sizeof(double) * hh + hh;
+}
+
+// Operands of one site of an anti-diagonal that the pass leaves unchanged.
+struct StageSite {
+  double dF, u, lnu, sa, sb, sn[3], s0[3], xp[3], yp[3];
+  int f, c;
+  bool on, stage1;
+};
+
+__global__ __launch_bounds__(64) void decide_stage_kernel(
+    double* S, BlockGeom g, ModelParams m, SweepRef sr, int K, bool da,
+    const DecidePrep* __restrict__ prep, tca_update_record* __restrict__ log_base,
+    unsigned long long* __restrict__ counters) {
+  extern __shared__ double stage_lds[];
+  constexpr int PW = (int)(sizeof(DecidePrep) / sizeof(double));
+  static_assert(sizeof(DecidePrep) % sizeof(double) == 0, "records are whole doubles");
+  const int h = g.h, L = g.L, hf = h + 2, hh = h * h, lane = threadIdx.x;
+  DecidePrep* pl = reinterpret_cast<DecidePrep*>(stage_lds);
+  double* fr = stage_lds + PW * hh;     // frame spins, 3 per site
+  double* dEs = fr + 3 * hf * hf;       // dE per site
+  uint8_t* accb = reinterpret_cast<uint8_t*>(dEs + hh);  // decision per site
+  {
+    // batches of loads issued together, so the staging costs a few memory
+    // latencies rather than one per element
+    constexpr int BF = 8, BP = 16;
+    for (int f0 = 0; f0 < hf * hf; f0 += 64 * BF) {
+      double v[BF][3];
+#pragma unroll
+      for (int u = 0; u < BF; ++u) {
+        const int f = f0 + lane + 64 * u;
+        const int px = (g.x0 + f % hf - 1 + L) % L, py = (g.y0 + f / hf - 1 + L) % L;
+        const double* sp = S + 3 * (px + L * py);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[u][k] = f < hf * hf ? sp[k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BF; ++u) {
+        const int f = f0 + lane + 64 * u;
+        if (f < hf * hf) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) fr[3 * f + k] = v[u][k];
+        }
+      }
+    }
+    const double* src = reinterpret_cast<const double*>(prep);
+    const int nw = PW * hh;
+    for (int w0 = 0; w0 < nw; w0 += 64 * BP) {
+      double v[BP];
+#pragma unroll
+      for (int u = 0; u < BP; ++u) {
+        const int w = w0 + lane + 64 * u;
+        v[u] = w < nw ? src[w] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BP; ++u) {
+        const int w = w0 + lane + 64 * u;
+        if (w < nw) stage_lds[w] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const double T = sr.T(), invT = 1.0 / T;
+  const int nd = 2 * h - 1;
+  auto fetch = [&](const int dd, StageSite& st) {
+    const int lo = max(0, dd - (h - 1));
+    const int cnt = min(dd, h - 1) - lo + 1;
+    st.on = dd < nd && lane < cnt;
+    if (!st.on) return;
+    const int i = lo + lane, j = dd - i;
+    st.c = i + h * j;
+    st.f = (i + 1) + hf * (j + 1);
+    const DecidePrep& pr = pl[st.c];
+    st.stage1 = (pr.flags & 2) != 0;
+    st.dF = pr.dF;
+    st.u = pr.u;
+    st.lnu = pr.lnu;
+    st.sa = pr.sa;
+    st.sb = pr.sb;
+    for (int k = 0; k < 3; ++k) {
+      st.sn[k] = pr.sn[k];
+      st.s0[k] = fr[3 * st.f + k];
+      st.xp[k] = fr[3 * (st.f + 1) + k];
+      st.yp[k] = fr[3 * (st.f + hf) + k];
+    }
+  };
+  // anti-diagonal dd from cur; the unchanged operands of dd + 1 go to nxt
+  auto diagonal = [&](const int dd, const StageSite& cur, StageSite& nxt) {
+    if (cur.on) {
+      double a[3], b[3];
+      for (int k = 0; k < 3; ++k) {
+        a[k] = fr[3 * (cur.f - 1) + k];
+        b[k] = fr[3 * (cur.f - hf) + k];
+      }
+      double dE = __builtin_nan("");
+      bool acc = false;
+      if (cur.stage1) {
+        dE = cur.dF + classical_term(a, cur.xp, b, cur.yp, cur.s0, cur.sn, m.JAF);
+        acc = metropolis_accept(cur.u, cur.lnu, cur.sa, cur.sb, dE, T, invT, da);
+      }
+      if (acc) {
+        for (int k = 0; k < 3; ++k) fr[3 * cur.f + k] = cur.sn[k];
+      }
+      dEs[cur.c] = dE;
+      accb[cur.c] = acc ? 1 : 0;
+    }
+    fetch(dd + 1, nxt);
+    // the next anti-diagonal reads this one's frame entries: order the LDS only
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  };
+  StageSite w0, w1;
+  fetch(0, w0);
+  for (int dd = 0; dd < nd; dd += 2) {
+    diagonal(dd, w0, w1);
+    if (dd + 1 < nd) diagonal(dd + 1, w1, w0);
+  }
+  // spins, flags, records and counters of the whole block
+  tca_update_record* logbuf =
+      log_base != nullptr ? log_base + (size_t)sr.s() * (size_t)L * (size_t)L : nullptr;
+  unsigned nacc = 0, nnear = 0, npass = 0;
+  for (int c = lane; c < hh; c += 64) {
+    const DecidePrep& pr = pl[c];
+    const bool stage1 = (pr.flags & 2) != 0, acc = accb[c] != 0;
+    const double dE = dEs[c];
+    const bool near = stage1 && metropolis_near(pr.u, pr.lnu, pr.sa, pr.sb, dE, T, da);
+    const int site = (g.x0 + c % h) + L * (g.y0 + c / h);
+    if (acc) {
+      for (int k = 0; k < 3; ++k) S[3 * site + k] = pr.sn[k];
+    }
+    nacc += acc;
+    nnear += near;
+    npass += stage1;
+    if (logbuf != nullptr) {
+      tca_update_record rec;
+      rec.site = site;
+      rec.Lc = pr.Lc;
+      rec.accept = acc ? 1 : 0;
+      rec.flags = (uint8_t)((near ? 1 : 0) | pr.flags);
+      rec.dF = pr.dF;
+      rec.dE = dE;
+      rec.u = pr.u;
+      rec.dS_f = pr.dSf;
+      rec.dS_r = pr.dSr;
+      logbuf[(size_t)K * h * h + c] = rec;
+    }
+  }
+  add_wave_total(&counters[0], nacc);
+  add_wave_total(&counters[1], nnear);
+  add_wave_total(&counters[3], npass);
+  if (lane == 0) atomicAdd(&counters[2], (unsigned long long)(h * h));
 }
 
 __global__ void classify_kernel(int4 classes, int n_classes, BlockGeom g, uint64_t seed,
@@ -433,7 +644,10 @@ hipError_t launch_decide(double* S, const double* Fpair, BlockGeom g, ModelParam
   const int hh = g.h * g.h;
   hipLaunchKernelGGL(decide_prep_kernel, dim3((hh + 255) / 256), dim3(256), 0, st, Fpair, g, m, sr,
                      Lc_fixed, pack_classes(classes_Lc, n_classes), n_classes, pass, dS, prep);
-  if (m.JAF != 0.0 && g.h <= kWaveMaxH)
+  if (m.JAF != 0.0 && g.h <= kStageMaxH)
+    hipLaunchKernelGGL(decide_stage_kernel, dim3(1), dim3(64), decide_stage_lds_bytes(g.h), st, S,
+                       g, m, sr, K, pass != nullptr, (const DecidePrep*)prep, log_base, counters);
+  else if (m.JAF != 0.0 && g.h <= kWaveMaxH)
     hipLaunchKernelGGL(decide_wave_kernel, dim3(1), dim3(kWaveMaxH), 0, st, S, g, m, sr, K,
                        pass != nullptr, (const DecidePrep*)prep, log_base, counters);
   else

@@ -27,29 +27,6 @@
 
 namespace tca {
 
-struct TriBounds {
-  double lo, hi, tol;
-};
-
-// Gershgorin bounds widened by a few ulps.
-__device__ inline TriBounds tri_bounds(const int n, const double* d, const double* e2) {
-  double lo = DBL_MAX, hi = -DBL_MAX;
-  double ep = 0.0;  // |e_{i-1}|
-  for (int i = 0; i < n; ++i) {
-    const double en = (i < n - 1) ? sqrt(e2[i]) : 0.0;
-    lo = fmin(lo, d[i] - ep - en);
-    hi = fmax(hi, d[i] + ep + en);
-    ep = en;
-  }
-  TriBounds b;
-  const double span = fmax(fmax(fabs(lo), fabs(hi)), DBL_MIN);
-  const double widen = 2.0 * DBL_EPSILON * span * (double)n;
-  b.lo = lo - widen;
-  b.hi = hi + widen;
-  b.tol = 2.0 * DBL_EPSILON * span;
-  return b;
-}
-
 __device__ __forceinline__ unsigned sign_change(double a, double b) {
   return (unsigned)(__double2hiint(a) ^ __double2hiint(b)) >> 31;
 }
@@ -59,138 +36,18 @@ __device__ __forceinline__ double rescale_factor(double m) {
   return m > 0x1p200 ? 0x1p-200 : (m < 0x1p-200 && m > 0.0 ? 0x1p200 : 1.0);
 }
 
-constexpr int kSturmGroup = 8;  // steps between rescalings (one scalar-load wait each)
+constexpr int kSturmGroup = 8;  // steps between rescalings
 
-// Number of eigenvalues below x.
-__device__ __forceinline__ int sturm_count(const int n, const double x, const double* d,
-                                           const double* e2) {
-  double pm = 1.0, p = d[0] - x;
-  unsigned c = sign_change(p, pm);
-  int i = 1;
-  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
-    double dd[kSturmGroup], ee[kSturmGroup];
-#pragma unroll
-    for (int u = 0; u < kSturmGroup; ++u) {
-      dd[u] = d[i + u];
-      ee[u] = e2[i + u - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kSturmGroup; ++u) {
-      const double pn = fma(dd[u] - x, p, -ee[u] * pm);
-      c += sign_change(pn, p);
-      pm = p;
-      p = pn;
-    }
-    const double f = rescale_factor(fmax(fabs(p), fabs(pm)));
-    p *= f;
-    pm *= f;
-  }
-  for (; i < n; ++i) {
-    const double pn = fma(d[i] - x, p, -e2[i - 1] * pm);
-    c += sign_change(pn, p);
-    pm = p;
-    p = pn;
-  }
-  return (int)c;
+// The sign bits of the minors enter a shift register, one funnel shift per
+// step: bits = bits << 1 | sign(P_i).  The sign changes of a group of G steps
+// are then the set bits of bits ^ (bits >> 1) in its low G positions (bit G
+// holds the sign before the group).
+__device__ __forceinline__ unsigned push_sign(unsigned bits, double p) {
+  return __builtin_amdgcn_alignbit(bits, (unsigned)__double2hiint(p), 31);
 }
-
-// Sturm count at x and the Newton step P_n/P_n' for det(T - x).
-__device__ __forceinline__ int sturm_newton(const int n, const double x, const double* d,
-                                            const double* e2, double* step) {
-  double pm = 1.0, p = d[0] - x;
-  double qm = 0.0, q = -1.0;  // derivatives
-  unsigned c = sign_change(p, pm);
-  int i = 1;
-  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
-    double dd[kSturmGroup], ee[kSturmGroup];
-#pragma unroll
-    for (int u = 0; u < kSturmGroup; ++u) {
-      dd[u] = d[i + u];
-      ee[u] = e2[i + u - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kSturmGroup; ++u) {
-      const double dx = dd[u] - x, e = ee[u];
-      const double pn = fma(dx, p, -e * pm);
-      const double qn = fma(dx, q, -fma(e, qm, p));
-      c += sign_change(pn, p);
-      pm = p;
-      p = pn;
-      qm = q;
-      q = qn;
-    }
-    const double f = rescale_factor(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))));
-    p *= f;
-    pm *= f;
-    q *= f;
-    qm *= f;
-  }
-  for (; i < n; ++i) {
-    const double dx = d[i] - x, e = e2[i - 1];
-    const double pn = fma(dx, p, -e * pm);
-    const double qn = fma(dx, q, -fma(e, qm, p));
-    c += sign_change(pn, p);
-    pm = p;
-    p = pn;
-    qm = q;
-    q = qn;
-  }
-  *step = p / q;
-  return (int)c;
-}
-
-// Eigenvalue j of T.
-__device__ inline double tri_eigenvalue(const int n, const int j, const double* d, const double* e2,
-                                        const TriBounds& B) {
-  double a = B.lo, b = B.hi;
-  int ca = 0, cb = n;
-  int extra = 2;
-  while (b - a > B.tol) {
-    if (ca == j && cb == j + 1 && extra-- <= 0) break;
-    const double mid = 0.5 * (a + b);
-    if (mid <= a || mid >= b) break;
-    const int c = sturm_count(n, mid, d, e2);
-    if (c > j) {
-      b = mid;
-      cb = c;
-    } else {
-      a = mid;
-      ca = c;
-    }
-  }
-  if (b - a <= B.tol) return 0.5 * (a + b);
-  double x = 0.5 * (a + b);
-  double last = b - a;
-  for (int it = 0; it < 12; ++it) {
-    double step;
-    const int c = sturm_newton(n, x, d, e2, &step);
-    if (c > j)
-      b = x;
-    else
-      a = x;
-    if (b - a <= B.tol) return 0.5 * (a + b);
-    double xn = x - step;
-    const bool inside = xn > a && xn < b;
-    const double st = fabs(step);
-    if (st <= B.tol) return xn;
-    // a small step that no longer halves, or that points out of the bracket,
-    // is rounding noise of det(T - x): x is as accurate as a bisection to the
-    // tolerance (in the quadratic regime a step of 1e5 tol is followed by one
-    // far below half of it)
-    if (st <= 1e5 * B.tol && (st > 0.5 * last || !inside)) return x;
-    if (!inside) xn = 0.5 * (a + b);
-    last = inside ? st : b - a;
-    x = xn;
-  }
-  while (b - a > B.tol) {
-    const double mid = 0.5 * (a + b);
-    if (mid <= a || mid >= b) break;
-    if (sturm_count(n, mid, d, e2) > j)
-      b = mid;
-    else
-      a = mid;
-  }
-  return 0.5 * (a + b);
+template <int G>
+__device__ __forceinline__ unsigned group_changes(unsigned bits) {
+  return (unsigned)__builtin_popcount((bits ^ (bits >> 1)) & ((1u << G) - 1u));
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +57,8 @@ __device__ inline double tri_eigenvalue(const int n, const int j, const double* 
 __device__ __forceinline__ int sturm_count_pairs(const int n, const double x,
                                                  const double2* de) {
   double pm = 1.0, p = de[0].x - x;
-  unsigned c = sign_change(p, pm);
+  unsigned bits = push_sign(0u, p);  // P_0 = 1 is positive
+  unsigned c = bits & 1u;
   int i = 1;
   for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
     double2 q[kSturmGroup];
@@ -209,10 +67,11 @@ __device__ __forceinline__ int sturm_count_pairs(const int n, const double x,
 #pragma unroll
     for (int u = 0; u < kSturmGroup; ++u) {
       const double pn = fma(q[u].x - x, p, -q[u].y * pm);
-      c += sign_change(pn, p);
+      bits = push_sign(bits, pn);
       pm = p;
       p = pn;
     }
+    c += group_changes<kSturmGroup>(bits);
     const double f = rescale_factor(fmax(fabs(p), fabs(pm)));
     p *= f;
     pm *= f;
@@ -231,7 +90,8 @@ __device__ __forceinline__ int sturm_newton_pairs(const int n, const double x, c
                                                   double* step) {
   double pm = 1.0, p = de[0].x - x;
   double qm = 0.0, q = -1.0;
-  unsigned c = sign_change(p, pm);
+  unsigned bits = push_sign(0u, p);
+  unsigned c = bits & 1u;
   int i = 1;
   for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
     double2 r[kSturmGroup];
@@ -242,12 +102,13 @@ __device__ __forceinline__ int sturm_newton_pairs(const int n, const double x, c
       const double dx = r[u].x - x, e = r[u].y;
       const double pn = fma(dx, p, -e * pm);
       const double qn = fma(dx, q, -fma(e, qm, p));
-      c += sign_change(pn, p);
+      bits = push_sign(bits, pn);
       pm = p;
       p = pn;
       qm = q;
       q = qn;
     }
+    c += group_changes<kSturmGroup>(bits);
     const double f = rescale_factor(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))));
     p *= f;
     pm *= f;

@@ -254,6 +254,18 @@ def test_sweep_wide_block_decisions(lib):
     assert stats["bad"] == 0 and stats["max_rel"] <= REL_TOL
 
 
+@pytest.mark.parametrize("L", [48, 50])
+def test_decision_pass_at_staging_limit(lib, L):
+    """Blocks of side 24 (staged whole in LDS) and 25 (read one anti-diagonal
+    ahead from memory), J_AF != 0: every decision replayed by the oracle."""
+    rng = np.random.default_rng(L)
+    check = set(rng.choice(L * L, 8, replace=False).tolist())
+    res = run_lockstep(lib, L, 2, 0.05, 31, 0.1, 2, check=check)
+    for recs, stats, st in res:
+        assert stats["bad"] == 0 and stats["max_rel"] <= REL_TOL
+        assert 0 < st["accepted"] < L * L
+
+
 def test_zero_sweeps_is_noop(lib):
     lat = lib.Lattice(8, 4, seed=1)
     S0 = lat.spins()
