@@ -12,15 +12,14 @@
 // the same total count as replacing a zero pivot by a tiny negative one.
 //
 // Search.  Eigenvalue j (ascending) is bracketed by bisection only until
-// [a, b] holds eigenvalue j alone (and two more halvings); then Newton steps
-// on det(T - x) = P_n(x) finish it, the derivative P_n' coming from the
-// differentiated recurrence P'_{i+1} = -P_i + (d_i - x) P'_i - e2_{i-1} P'_{i-1}.
-// Every evaluation also gives the Sturm count that keeps the bracket; a Newton
-// iterate leaving the bracket is replaced by the midpoint.  Newton stops when
-// its step is below the tolerance, or is small and fails to halve or leaves
-// the bracket (the rounding noise of det(T - x) is reached); an eigenvalue
-// that cannot be isolated (a cluster narrower than the tolerance) is finished
-// by plain bisection.
+// [a, b] holds eigenvalue j alone; then Laguerre steps on det(T - x) = P_n(x)
+// finish it, P_n' and P_n'' coming from the recurrence differentiated once and
+// twice.  Every evaluation also gives the Sturm count that keeps the bracket;
+// an iterate leaving the bracket is replaced by the midpoint.  The iteration
+// stops when its step is below the tolerance, or is small and fails to halve
+// or leaves the bracket (the rounding noise of det(T - x) is reached); an
+// eigenvalue that cannot be isolated (a cluster narrower than the tolerance)
+// is finished by plain bisection.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <float.h>
@@ -86,58 +85,81 @@ __device__ __forceinline__ int sturm_count_pairs(const int n, const double x,
   return (int)c;
 }
 
-__device__ __forceinline__ int sturm_newton_pairs(const int n, const double x, const double2* de,
-                                                  double* step) {
+// Sturm count at x and the Laguerre step for det(T - x) = P_n(x), from P_n,
+// P_n' and P_n'' (the recurrence differentiated twice:
+// P''_{i+1} = -2 P'_i + (d_i - x) P''_i - e2_{i-1} P''_{i-1}).  With
+// G = P'/P and H = G^2 - P''/P the step is n / (G +- sqrt((n-1)(n H - G^2))),
+// the sign taken to make the denominator larger.  For a polynomial with real
+// roots only the iteration converges from any start and cubically near a
+// simple root, where the step tends to the Newton step P/P'.
+__device__ __forceinline__ int sturm_laguerre_pairs(const int n, const double x,
+                                                    const double2* de, double* step) {
   double pm = 1.0, p = de[0].x - x;
-  double qm = 0.0, q = -1.0;
+  double qm = 0.0, q = -1.0;  // first derivatives
+  double rm = 0.0, r = 0.0;   // second derivatives
   unsigned bits = push_sign(0u, p);
   unsigned c = bits & 1u;
   int i = 1;
   for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
-    double2 r[kSturmGroup];
+    double2 v[kSturmGroup];
 #pragma unroll
-    for (int u = 0; u < kSturmGroup; ++u) r[u] = de[i + u];
+    for (int u = 0; u < kSturmGroup; ++u) v[u] = de[i + u];
 #pragma unroll
     for (int u = 0; u < kSturmGroup; ++u) {
-      const double dx = r[u].x - x, e = r[u].y;
+      const double dx = v[u].x - x, e = v[u].y;
       const double pn = fma(dx, p, -e * pm);
       const double qn = fma(dx, q, -fma(e, qm, p));
+      const double rn = fma(dx, r, -fma(e, rm, 2.0 * q));
       bits = push_sign(bits, pn);
       pm = p;
       p = pn;
       qm = q;
       q = qn;
+      rm = r;
+      r = rn;
     }
     c += group_changes<kSturmGroup>(bits);
-    const double f = rescale_factor(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))));
+    const double f = rescale_factor(fmax(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))),
+                                         fmax(fabs(r), fabs(rm))));
     p *= f;
     pm *= f;
     q *= f;
     qm *= f;
+    r *= f;
+    rm *= f;
   }
   for (; i < n; ++i) {
     const double dx = de[i].x - x, e = de[i].y;
     const double pn = fma(dx, p, -e * pm);
     const double qn = fma(dx, q, -fma(e, qm, p));
+    const double rn = fma(dx, r, -fma(e, rm, 2.0 * q));
     c += sign_change(pn, p);
     pm = p;
     p = pn;
     qm = q;
     q = qn;
+    rm = r;
+    r = rn;
   }
-  *step = p / q;
+  if (p == 0.0) {
+    *step = 0.0;  // x is an eigenvalue
+  } else {
+    const double nd = (double)n, G = q / p, H = G * G - r / p;
+    const double s = sqrt(fmax((nd - 1.0) * (nd * H - G * G), 0.0));
+    const double den = fabs(G + s) >= fabs(G - s) ? G + s : G - s;
+    *step = nd / den;  // den == 0 gives an infinite step, which the bracket rejects
+  }
   return (int)c;
 }
 
-constexpr double kNewtonLastStep = 2.25e6;  // ~1e-9 / (2 eps)
+constexpr double kLastStep = 2.25e6;  // ~1e-9 / (2 eps)
 
 // Eigenvalue j of T from a bracket [a, b] with counts ca <= j < cb.
 __device__ inline double tri_eigenvalue_pairs(const int n, const int j, const double2* de,
                                               double a, double b, int ca, int cb,
                                               const double tol) {
-  int extra = 2;
   while (b - a > tol) {
-    if (ca == j && cb == j + 1 && extra-- <= 0) break;
+    if (ca == j && cb == j + 1) break;
     const double mid = 0.5 * (a + b);
     if (mid <= a || mid >= b) break;
     const int c = sturm_count_pairs(n, mid, de);
@@ -154,7 +176,7 @@ __device__ inline double tri_eigenvalue_pairs(const int n, const int j, const do
   double last = b - a;
   for (int it = 0; it < 12; ++it) {
     double step;
-    const int c = sturm_newton_pairs(n, x, de, &step);
+    const int c = sturm_laguerre_pairs(n, x, de, &step);
     if (c > j)
       b = x;
     else
@@ -164,10 +186,11 @@ __device__ inline double tri_eigenvalue_pairs(const int n, const int j, const do
     const bool inside = xn > a && xn < b;
     const double st = fabs(step);
     if (st <= tol) return xn;
-    // near a simple root the error after a Newton step of size st is of order
-    // st^2 / (root spacing): a step below ~1e-9 of the spectral scale (tol is
-    // 2 eps of it) leaves an error far below tol, so it is the last one
-    if (inside && st <= kNewtonLastStep * tol) return xn;
+    // near a simple root the error after a step of size st is of order
+    // st^3 / (root spacing)^2 (at most st^2 / spacing, as for Newton): a step
+    // below ~1e-9 of the spectral scale (tol is 2 eps of it) leaves an error
+    // far below tol, so it is the last one
+    if (inside && st <= kLastStep * tol) return xn;
     if (st <= 1e5 * tol && (st > 0.5 * last || !inside)) return x;
     if (!inside) xn = 0.5 * (a + b);
     last = inside ? st : b - a;
