@@ -130,33 +130,49 @@ __device__ __forceinline__ float rsqrt_nr(float s) {
   return fmaf(0.5f * r, e, r);
 }
 
-// Column k+1 of A^{(k+1)}, d_{k+1}, e_{k+1}^2, reflector k+1 into vn and
-// (tre, tim).  v_k and w_k are read back from this wavefront's LDS copies,
-// so nothing but (tau_k, a2) stays live across the register update.
+// The operands of the reflector of step k that are ready when the step
+// begins: column k+1 of A^{(k)} (rows lane + 64 q) and the entries k+1, k+2
+// of that column, of y_k and of v_k.
+template <int NQ, typename R>
+struct ReflectIn {
+  cx<R> cv[NQ];
+  cx<R> c1, c2, y1, y2, v2;
+};
+template <int NP, int NQ, typename R, class Smem>
+__device__ __forceinline__ ReflectIn<NQ, R> reflect_in(const int k, const Smem& sm,
+                                                       const cx<R>* __restrict__ vk) {
+  const int lane = threadIdx.x & 63, k1 = k + 1;
+  const cx<R>* colk = sm.col[(k + 1) & 1];
+  const cx<R>* yk = sm.y[k & 1];
+  ReflectIn<NQ, R> o;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    o.cv[q] = colk[i < NP ? i : NP - 1];
+  }
+  o.c1 = colk[k1];
+  o.c2 = colk[k1 + 1];
+  o.y1 = yk[k1];
+  o.y2 = yk[k1 + 1];
+  o.v2 = vk[k1 + 1];
+  return o;
+}
+
+// Column k+1 of A^{(k+1)}, d_{k+1}, e_{k+1}^2, reflector k+1 into this
+// wavefront's copy of v_{k+1} and (tre, tim), from the operands read when the
+// step began and this wavefront's rows of v_k and w_k (vv, wv) in registers.
 template <int NP, int NQ, typename R, class Smem>
 __device__ __forceinline__ void split_reflect(const int n, const int k, Smem& sm, const R a2, R& tre,
-                                            R& tim) {
+                                            R& tim, const ReflectIn<NQ, R>& in,
+                                            const cx<R> (&vv)[NQ], const cx<R> (&wv)[NQ]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, k1 = k + 1;
-  const cx<R>* colk = sm.col[(k + 1) & 1];
-  const cx<R>* vk = sm.vb[wave][k & 1];
-  const cx<R>* wb = sm.wb[wave];
-  const cx<R>* yk = sm.y[k & 1];
   cx<R>* vn = sm.vb[wave][(k + 1) & 1];
-  const cx<R> c1 = colk[k1], c2 = colk[k1 + 1];
-  const cx<R> y1 = yk[k1], y2 = yk[k1 + 1], v2 = vk[k1 + 1];
+  const cx<R> c1 = in.c1, c2 = in.c2, y1 = in.y1, y2 = in.y2, v2 = in.v2;
   // w_k[k+1] (v_k[k+1] = 1 whenever tau_k != 0) and w_k[k+2]
   const cx<R> wk1 = {fma(tre, y1.re, fma(-tim, y1.im, -a2)), fma(tre, y1.im, tim * y1.re)};
   const cx<R> wk2 = {fma(tre, y2.re, fma(-tim, y2.im, -a2 * v2.re)),
                      fma(tre, y2.im, fma(tim, y2.re, -a2 * v2.im))};
-  cx<R> cv[NQ], vv[NQ], wv[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int i = lane + 64 * q;
-    const int ic = i < NP ? i : NP - 1;
-    cv[q] = colk[ic];
-    vv[q] = vk[ic];
-    wv[q] = wb[ic];
-  }
+  const cx<R>(&cv)[NQ] = in.cv;
   // x_i = col_i - v_k[i] conj(w_k[k+1]) - w_k[i]
   cx<R> xreg[NQ];
   R s2 = R(0);
@@ -402,8 +418,9 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
   }
 
   static __device__ __forceinline__ void reflect(const int n, const int k, Smem& sm, const R a2,
-                                                 R& tre, R& tim) {
-    split_reflect<NP, NQ>(n, k, sm, a2, tre, tim);
+                                                 R& tre, R& tim, const ReflectIn<NQ, R>& in,
+                                                 const cx<R> (&vv)[NQ], const cx<R> (&wv)[NQ]) {
+    split_reflect<NP, NQ>(n, k, sm, a2, tre, tim, in, vv, wv);
   }
 
   template <int P>
@@ -436,6 +453,10 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
       vv[q] = vk[ic];
       yv[q] = yk[ic];
     }
+    // the reflector's LDS operands are read with these (with LD after the
+    // leaders' matrix-core issue, which measured faster there)
+    ReflectIn<NQ, R> rin;
+    if (!LD) rin = reflect_in<NP, NQ>(k, sm, vk);
     R c = R(0);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -445,13 +466,13 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
     }
     c = wave_total_rows(c);
     const R a2 = R(0.5) * (tre * tre + tim * tim) * c;
+    cx<R> wv[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      cx<R> w;
-      w.re = fma(tre, yv[q].re, fma(-tim, yv[q].im, -a2 * vv[q].re));
-      w.im = fma(tre, yv[q].im, fma(tim, yv[q].re, -a2 * vv[q].im));
+      wv[q].re = fma(tre, yv[q].re, fma(-tim, yv[q].im, -a2 * vv[q].re));
+      wv[q].im = fma(tre, yv[q].im, fma(tim, yv[q].re, -a2 * vv[q].im));
       const int i = lane + 64 * q;
-      if (NP % 64 == 0 || i < NP) wb[i] = w;
+      if (NP % 64 == 0 || i < NP) wb[i] = wv[q];
     }
     wave_lds_fence();
     // ---- (2) reflector and (3) update
@@ -459,9 +480,15 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
       // followers: the update only, while the leaders build the reflector
       if constexpr (MF) {
         mf_tiles<P, LC>(A, mf_ops<P>(vk, wb));
-        if (leader) reflect(n, k, sm, a2, tre, tim);
+        if (leader) {
+          rin = reflect_in<NP, NQ>(k, sm, vk);
+          reflect(n, k, sm, a2, tre, tim, rin, vv, wv);
+        }
       } else {
-        if (leader) reflect(n, k, sm, a2, tre, tim);
+        if (leader) {
+          rin = reflect_in<NP, NQ>(k, sm, vk);
+          reflect(n, k, sm, a2, tre, tim, rin, vv, wv);
+        }
         valu_update<P / RATIO, P>(A, vk, wb);
       }
       if (tid == 0) {
@@ -477,11 +504,11 @@ struct ReduceSplit : ReduceFused<TR, TC, LR, LC, R, MW, false> {
       // the last VT column blocks of the update on the vector ALUs, after (2)
       constexpr int JE = LC - VT > P ? LC - VT : P;
       mf_tiles<P, JE>(A, mf_ops<P>(vk, wb));
-      reflect(n, k, sm, a2, tre, tim);
+      reflect(n, k, sm, a2, tre, tim, rin, vv, wv);
       if constexpr (JE < LC) valu_update<P / RATIO, JE>(A, vk, wb);
       wave_lds_fence();
     } else {
-      reflect(n, k, sm, a2, tre, tim);
+      reflect(n, k, sm, a2, tre, tim, rin, vv, wv);
       valu_update<P / RATIO, P>(A, vk, wb);
       wave_lds_fence();
     }
