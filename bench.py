@@ -35,14 +35,14 @@ PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop
 # variant runs there) scaled by the calibration transfers (FETCH_SIZE x 1.996, WRITE_SIZE x
 # 1.0); re-measure whenever a kernel changes.
 TRAFFIC_BYTES_FP64_REDUCE = {
-    "fused 32x16 grid": 2.469e6,
-    "two-pass 32x16 grid": 2.030e6,
-    "fused 32x16 grid, rank-2 update on MFMA": 5.045e6,
-    "split 32x16 grid": 2.336e6,
-    "split 32x16 grid, rank-2 update on MFMA": 2.254e6,
-    "split 32x16 grid, rank-2 update on MFMA and vector ALUs": 2.302e6,
-    "split 32x16 grid, rank-2 update on MFMA, reflector on half the wavefronts": 2.267e6,
-    "split 32x16 grid, reflector on half the wavefronts": 2.338e6,
+    "fused 32x16 grid": 2.465e6,
+    "two-pass 32x16 grid": 2.008e6,
+    "fused 32x16 grid, rank-2 update on MFMA": 5.049e6,
+    "split 32x16 grid": 2.334e6,
+    "split 32x16 grid, rank-2 update on MFMA": 2.240e6,
+    "split 32x16 grid, rank-2 update on MFMA and vector ALUs": 2.298e6,
+    "split 32x16 grid, rank-2 update on MFMA, reflector on half the wavefronts": 2.266e6,
+    "split 32x16 grid, reflector on half the wavefronts": 2.320e6,
 }
 
 
