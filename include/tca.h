@@ -58,6 +58,9 @@ enum {
   TCA_FLAG_PROFILE = 1,      /* time every kernel launch of a sweep with HIP events */
   TCA_FLAG_NO_GRAPH = 2,     /* issue every launch directly instead of replaying a captured sweep */
   TCA_FLAG_NO_AUTOTUNE = 4,  /* keep the default reducer variants (no timing at init) */
+  TCA_FLAG_EXACT_METROPOLIS = 8, /* evaluate every Metropolis test in its exact form (u < exp(-dE/T),
+                                    or the delayed-acceptance quotient) instead of comparing ln u with
+                                    -dE/T outside a relative 1e-10 band; the decisions are the same */
 };
 
 typedef struct {

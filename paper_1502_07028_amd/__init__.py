@@ -18,7 +18,7 @@ TCA_ABI_VERSION = 2
 TCA_OK, TCA_E_INVAL, TCA_E_NOMEM, TCA_E_DEVICE, TCA_E_UNSUPPORTED = 0, -1, -2, -3, -4
 TCA_FP64, TCA_MIXED = 0, 1
 TCA_INIT_RANDOM, TCA_INIT_FERRO, TCA_INIT_NEEL, TCA_INIT_USER = 0, 1, 2, 3
-TCA_FLAG_PROFILE, TCA_FLAG_NO_GRAPH, TCA_FLAG_NO_AUTOTUNE = 1, 2, 4
+TCA_FLAG_PROFILE, TCA_FLAG_NO_GRAPH, TCA_FLAG_NO_AUTOTUNE, TCA_FLAG_EXACT_METROPOLIS = 1, 2, 4, 8
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "

@@ -92,7 +92,8 @@ static void free_ctx(tca_ctx* c) {
 }
 
 static ModelParams model_of(const tca_ctx* c) {
-  return ModelParams{c->p.t, c->p.JH, c->p.JAF, c->p.mu, c->p.seed};
+  const double gap = (c->p.flags & TCA_FLAG_EXACT_METROPOLIS) ? HUGE_VAL : kDecideGap;
+  return ModelParams{c->p.t, c->p.JH, c->p.JAF, c->p.mu, c->p.seed, gap};
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -244,7 +245,7 @@ int tca_init_lattice(const tca_params* p, const double* spins_xyz, void* hip_str
       TCA_INVAL("every size class must satisfy 2 <= Lc <= min(10, L/2+1)");
   if (p->precision != TCA_FP64 && p->precision != TCA_MIXED) TCA_INVAL("bad precision");
   if (p->init < TCA_INIT_RANDOM || p->init > TCA_INIT_USER) TCA_INVAL("bad init");
-  if (p->flags & ~(TCA_FLAG_PROFILE | TCA_FLAG_NO_GRAPH | TCA_FLAG_NO_AUTOTUNE))
+  if (p->flags & ~(TCA_FLAG_PROFILE | TCA_FLAG_NO_GRAPH | TCA_FLAG_NO_AUTOTUNE | TCA_FLAG_EXACT_METROPOLIS))
     TCA_INVAL("unknown flag bits");
   if (!is_fin(p->t) || !is_fin(p->JH) || !is_fin(p->JAF) || !is_fin(p->mu))
     TCA_INVAL("model parameters must be finite");

@@ -22,7 +22,12 @@ struct BlockGeom {
 struct ModelParams {
   double t, JH, JAF, mu;
   uint64_t seed;
+  double decide_gap;  // relative band around the Metropolis threshold decided by the exact form
 };
+
+// Default band: outside it ln u and -dE/T differ by far more than the rounding
+// of log, exp and the quotient, so the comparison of logarithms decides.
+constexpr double kDecideGap = 1e-10;
 
 // Size classes of one block, filled on the device: list[k][*] holds the
 // cluster indices c whose drawn size is class k.

@@ -121,24 +121,24 @@ __global__ __launch_bounds__(256) void decide_prep_kernel(const double* __restri
 // threshold the decision is taken from ln u against -dE * (1/T): the two sides
 // then differ by far more than the rounding of the logarithm, the exponential
 // and the quotient, so the result is the one of the exact form, which is
-// evaluated only within a relative 1e-10 of the threshold.
-constexpr double kDecideGap = 1e-10;
-
+// evaluated only within a relative band gap (kDecideGap = 1e-10; infinite
+// with TCA_FLAG_EXACT_METROPOLIS) of the threshold.
 __device__ __forceinline__ bool metropolis_accept(const double u, const double lnu,
                                                   const double sa, const double sb,
                                                   const double dE, const double T,
-                                                  const double invT, const bool da) {
+                                                  const double invT, const bool da,
+                                                  const double gap_rel) {
   if (!da) {
     if (dE <= 0.0) return true;
     if (!(u > 0.0)) return u < exp(-dE / T);
     const double z = -dE * invT;
-    const double gap = lnu - z, tol = kDecideGap * (1.0 + fabs(z));
+    const double gap = lnu - z, tol = gap_rel * (1.0 + fabs(z));
     return gap < -tol ? true : (gap > tol ? false : u < exp(-dE / T));
   }
   if (u <= 0.0) return true;
   const double z = fma(-dE, invT, sa - sb);
   const double gap = lnu - z;
-  const double tol = kDecideGap * (1.0 + fabs(dE * invT) + fabs(sa) + fabs(sb));
+  const double tol = gap_rel * (1.0 + fabs(dE * invT) + fabs(sa) + fabs(sb));
   return gap < -tol ? true : (gap > tol ? false : lnu < -dE / T + sa - sb);
 }
 
@@ -156,9 +156,9 @@ __device__ __forceinline__ bool metropolis_near(const double u, const double lnu
 
 __device__ __forceinline__ bool metropolis_decide(const DecidePrep& pr, const double dE,
                                                   const double T, const double invT,
-                                                  const bool da, bool& near) {
+                                                  const bool da, const double gap_rel, bool& near) {
   near = metropolis_near(pr.u, pr.lnu, pr.sa, pr.sb, dE, T, da);
-  return metropolis_accept(pr.u, pr.lnu, pr.sa, pr.sb, dE, T, invT, da);
+  return metropolis_accept(pr.u, pr.lnu, pr.sa, pr.sb, dE, T, invT, da, gap_rel);
 }
 
 // Adds the wavefront total of a per-thread count to *p with one atomic from
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(1024) void decide_kernel(double* S, BlockGeom g, Mo
       bool acc = false, near = false;
       if (stage1) {
         dE = pr.dF + classical_delta(S, L, px, py, pr.sn, m.JAF);
-        acc = metropolis_decide(pr, dE, T, invT, da, near);
+        acc = metropolis_decide(pr, dE, T, invT, da, m.decide_gap, near);
         if (acc) {
           S[3 * site + 0] = pr.sn[0];
           S[3 * site + 1] = pr.sn[1];
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kWaveMaxH) void decide_wave_kernel(
       bool acc = false, near = false;
       if (stage1) {
         dE = pr.dF + classical_term(a, cur.xp, c, cur.yp, cur.s, pr.sn, m.JAF);
-        acc = metropolis_decide(pr, dE, T, invT, da, near);
+        acc = metropolis_decide(pr, dE, T, invT, da, m.decide_gap, near);
       }
       for (int k = 0; k < 3; ++k) fin[dd & 1][cur.i][k] = acc ? pr.sn[k] : cur.s[k];
       if (acc) {
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(64) void decide_stage_kernel(
       bool acc = false;
       if (cur.stage1) {
         dE = cur.dF + classical_term(a, cur.xp, b, cur.yp, cur.s0, cur.sn, m.JAF);
-        acc = metropolis_accept(cur.u, cur.lnu, cur.sa, cur.sb, dE, T, invT, da);
+        acc = metropolis_accept(cur.u, cur.lnu, cur.sa, cur.sb, dE, T, invT, da, m.decide_gap);
       }
       if (acc) {
         for (int k = 0; k < 3; ++k) fr[3 * cur.f + k] = cur.sn[k];

@@ -49,7 +49,7 @@ def test_struct_layouts_match():
     (dict(L=8, Lc=4, precision=5), "precision"),
     (dict(L=8, Lc=4, Lc_classes=(4, 6)), "size class"),
     (dict(L=8, Lc=4, JH=float("nan")), "finite"),
-    (dict(L=8, Lc=4, flags=8), "flag"),
+    (dict(L=8, Lc=4, flags=16), "flag"),
 ])
 def test_init_rejects_bad_params(kw, msg):
     import paper_1502_07028_amd as tca

@@ -266,6 +266,24 @@ def test_decision_pass_at_staging_limit(lib, L):
         assert 0 < st["accepted"] < L * L
 
 
+@pytest.mark.parametrize("L,Lc,JAF", [(8, 4, 0.05), (8, 4, 0.0), (50, 2, 0.05)])
+def test_metropolis_fast_path_equals_exact_form(lib, L, Lc, JAF):
+    """Decisions taken from ln u away from the threshold equal those of the
+    exact form (u < exp(-dE/T) for every update, TCA_FLAG_EXACT_METROPOLIS):
+    spins and update records bitwise, for the staged (side 4), memory-fed
+    (side 25) and independent (J_AF = 0) decision kernels."""
+    out = []
+    for flags in (0, lib.TCA_FLAG_EXACT_METROPOLIS):
+        lat = lib.Lattice(L, Lc, seed=41, JH=8.0, JAF=JAF, flags=flags)
+        recs = [lat.sweep([0.05], log=True)[0] for _ in range(2)]
+        out.append((lat.spins(), recs))
+        lat.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert a.tobytes() == b.tobytes()
+    assert 0 < int(sum(r["accept"].sum() for r in out[0][1])) < 2 * L * L
+
+
 def test_zero_sweeps_is_noop(lib):
     lat = lib.Lattice(8, 4, seed=1)
     S0 = lat.spins()

@@ -170,6 +170,26 @@ def test_delayed_acceptance_lockstep(lib, JAF, seed):
     sg.close()
 
 
+@pytest.mark.parametrize("JAF", [0.0, 0.05])
+def test_delayed_acceptance_exact_form_flag(lib, JAF):
+    """Second-stage decisions from ln u against the quotient equal the exact
+    form's (TCA_FLAG_EXACT_METROPOLIS) bitwise, with a surrogate attached."""
+    L, Lc, T = 8, 4, 0.05
+    out = []
+    for flags in (0, lib.TCA_FLAG_EXACT_METROPOLIS):
+        lat = lib.Lattice(L, Lc, seed=6, JAF=JAF, flags=flags)
+        sg = lib.Surrogate(Lc, 64, seed=6)
+        randomize(sg, 16, bias=0.5, out=(0.1, 0.05))
+        lat.attach(sg)
+        recs = [lat.sweep([T], log=True)[0] for _ in range(2)]
+        out.append((lat.spins(), recs))
+        lat.close()
+        sg.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert a.tobytes() == b.tobytes()
+
+
 def test_zero_surrogate_equals_plain_sweep(lib):
     L, Lc, T, seed = 12, 5, 0.05, 4
     a = lib.Lattice(L, Lc, seed=seed, JAF=0.05)
