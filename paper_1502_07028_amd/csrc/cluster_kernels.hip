@@ -141,11 +141,11 @@ __global__ __launch_bounds__(Red::NT, Red::MINW) void heevals_reduce(const doubl
 
 // One workgroup per tridiagonal (persistent over the matrices).  The matrix is
 // staged in LDS as (d_i, e2_{i-1}) pairs.  A first pass slices the spectrum:
-// thread t counts the eigenvalues below the t-th of NTHR evenly spaced points
-// of the Gershgorin interval, which brackets every eigenvalue to one slice;
-// then thread j finishes eigenvalues j, j + NTHR, ... from their slices
-// (bisection until isolated, then safeguarded Newton), and the grand
-// potential is reduced in a fixed order.
+// the threads count the eigenvalues below 4 NTHR evenly spaced points of the
+// Gershgorin interval (four interleaved counts per thread), which brackets
+// every eigenvalue to one slice; then thread j finishes eigenvalues j,
+// j + NTHR, ... from their slices (bisection until isolated, then safeguarded
+// Laguerre steps), and the grand potential is reduced in a fixed order.
 template <int NTHR>
 __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restrict__ D,
                                                            const double* __restrict__ E2, int ld,
@@ -156,8 +156,10 @@ __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restr
                                                            const int32_t* __restrict__ list,
                                                            const int32_t* __restrict__ count) {
   constexpr int NW = NTHR / 64;
+  constexpr int SPT = 4;             // slice points per thread
+  constexpr int NS = SPT * NTHR;     // slice points
   __shared__ double2 de[kMaxN];
-  __shared__ int cnt[NTHR];
+  __shared__ int cnt[NS];
   __shared__ double red[NW], wlo[NW], whi[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double T = sr.T();
@@ -199,14 +201,23 @@ __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restr
     lo -= widen;
     hi += widen;
     const double tol = 2.0 * DBL_EPSILON * span;
-    // slice the spectrum at x_t = lo + (t + 1) (hi - lo) / (NTHR + 1)
-    const double h = (hi - lo) / (double)(NTHR + 1);
-    cnt[tid] = sturm_count_pairs(n, fma((double)(tid + 1), h, lo), de);
+    // slice the spectrum at x_t = lo + (t + 1) (hi - lo) / (NS + 1), SPT points
+    // per thread counted together
+    const double h = (hi - lo) / (double)(NS + 1);
+    {
+      double xs[SPT];
+      int cs[SPT];
+#pragma unroll
+      for (int m = 0; m < SPT; ++m) xs[m] = fma((double)(tid + m * NTHR + 1), h, lo);
+      sturm_count_pairs_multi<SPT>(n, xs, de, cs);
+#pragma unroll
+      for (int m = 0; m < SPT; ++m) cnt[tid + m * NTHR] = cs[m];
+    }
     __syncthreads();
     double acc = 0.0;
     for (int j = tid; j < n; j += NTHR) {
       // last slice point with count <= j (counts are nondecreasing in x)
-      int lo_t = -1, hi_t = NTHR;  // cnt[lo_t] <= j < cnt[hi_t] (virtual ends 0 and n)
+      int lo_t = -1, hi_t = NS;  // cnt[lo_t] <= j < cnt[hi_t] (virtual ends 0 and n)
       while (hi_t - lo_t > 1) {
         const int mid = (lo_t + hi_t) >> 1;
         if (cnt[mid] <= j)
@@ -215,9 +226,9 @@ __global__ __launch_bounds__(NTHR) void tridiag_eig_kernel(const double* __restr
           hi_t = mid;
       }
       double a = lo_t < 0 ? lo : fma((double)(lo_t + 1), h, lo);
-      double b = hi_t >= NTHR ? hi : fma((double)(hi_t + 1), h, lo);
+      double b = hi_t >= NS ? hi : fma((double)(hi_t + 1), h, lo);
       int ca = lo_t < 0 ? 0 : cnt[lo_t];
-      int cb = hi_t >= NTHR ? n : cnt[hi_t];
+      int cb = hi_t >= NS ? n : cnt[hi_t];
       if (!(ca <= j && j < cb)) {  // a count that broke monotonicity: full interval
         a = lo;
         b = hi;

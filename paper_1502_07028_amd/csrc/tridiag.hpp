@@ -85,6 +85,57 @@ __device__ __forceinline__ int sturm_count_pairs(const int n, const double x,
   return (int)c;
 }
 
+// Counts at M points at once: M independent chains interleaved step by step,
+// which fills the latency of each chain's FMA with the others'.
+template <int M>
+__device__ __forceinline__ void sturm_count_pairs_multi(const int n, const double (&x)[M],
+                                                        const double2* de, int (&cnt)[M]) {
+  double pm[M], p[M];
+  unsigned bits[M], c[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    pm[m] = 1.0;
+    p[m] = de[0].x - x[m];
+    bits[m] = push_sign(0u, p[m]);
+    c[m] = bits[m] & 1u;
+  }
+  int i = 1;
+  for (; i + kSturmGroup - 1 < n; i += kSturmGroup) {
+    double2 q[kSturmGroup];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) q[u] = de[i + u];
+#pragma unroll
+    for (int u = 0; u < kSturmGroup; ++u) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const double pn = fma(q[u].x - x[m], p[m], -q[u].y * pm[m]);
+        bits[m] = push_sign(bits[m], pn);
+        pm[m] = p[m];
+        p[m] = pn;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      c[m] += group_changes<kSturmGroup>(bits[m]);
+      const double f = rescale_factor(fmax(fabs(p[m]), fabs(pm[m])));
+      p[m] *= f;
+      pm[m] *= f;
+    }
+  }
+  for (; i < n; ++i) {
+    const double2 q = de[i];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const double pn = fma(q.x - x[m], p[m], -q.y * pm[m]);
+      c[m] += sign_change(pn, p[m]);
+      pm[m] = p[m];
+      p[m] = pn;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) cnt[m] = (int)c[m];
+}
+
 // Sturm count at x and the Laguerre step for det(T - x) = P_n(x), from P_n,
 // P_n' and P_n'' (the recurrence differentiated twice:
 // P''_{i+1} = -2 P'_i + (d_i - x) P''_i - e2_{i-1} P''_{i-1}).  With
