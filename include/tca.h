@@ -48,7 +48,7 @@ typedef enum {
   TCA_E_INVAL = -1,        /* invalid argument (sizes, NULL, non-unit spin, ...) */
   TCA_E_NOMEM = -2,        /* device or host allocation failed */
   TCA_E_DEVICE = -3,       /* a HIP runtime call or kernel launch failed */
-  TCA_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  TCA_E_UNSUPPORTED = -4,  /* valid request the library does not implement */
 } tca_status;
 
 enum { TCA_FP64 = 0, TCA_MIXED = 1 };  /* precision of the tridiagonal reduction */
