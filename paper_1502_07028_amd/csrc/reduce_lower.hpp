@@ -9,7 +9,11 @@
 // lower triangle is stored (li >= lj, and inside a diagonal local block only
 // tr >= tc carries data, the rest stays zero).  y = A v is assembled from row
 // partials (lower part) and column partials (upper part, via conj(A_ji)) that
-// are summed through LDS.  The step algebra is that of reduce_full.hpp.
+// are summed through LDS.  The step algebra is that of reduce_full.hpp.  Both
+// the product and the rank-2 update walk the local blocks column block by
+// column block and read the row and column entries of v and w from LDS, so
+// that beside the matrix only the row partials of y live in registers (the
+// matrix takes most of the register file at n = 200 in FP64).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <float.h>
@@ -37,6 +41,9 @@ struct ReduceLower {
   static_assert(NT % 64 == 0, "workgroup must be whole wavefronts");
 
   static constexpr int MINW = 1;  // minimum wavefronts per SIMD (launch bounds)
+  // copies of v and w in LDS: one per wavefront (no barrier after writing
+  // them) up to four wavefronts, else one shared copy behind a barrier
+  static constexpr int NVC = NW <= 4 ? NW : 1;
 
   struct Smem {
     double d[NP];
@@ -45,6 +52,8 @@ struct ReduceLower {
     cx<R> y[NP];         // B v
     cx<R> pr[G * PITCH]; // row partials   [tc][i]
     cx<R> pc[G * PITCH]; // column partials [tr][j]
+    cx<R> vw[NVC][NP];   // v of the step (one copy per wavefront when they fit)
+    cx<R> ww[NVC][NP];   // w of the step
   };
 
   static __device__ __forceinline__ constexpr int idx(int li, int lj) { return li * (li + 1) / 2 + lj; }
@@ -67,26 +76,36 @@ struct ReduceLower {
 
   // Copy column k (rows k+1..n-1) of the register matrix to LDS; also write
   // the diagonal entry d[k] and, at the last column, the final 2x2 entries.
+  // The column block is tested once per block (a uniform branch) and the
+  // lanes of column k once inside it, instead of once per register entry.
   static __device__ __forceinline__ void write_col(int n, int k, const cx<R> (&A)[NLOC],
                                                    cx<R>* xb, double* d, double* e2) {
     const int tid = threadIdx.x, tr = tid / G, tc = tid % G;
     const int kb = k / G, kc = k % G;
 #pragma unroll
-    for (int li = 0; li < LR; ++li) {
+    for (int lj = 0; lj < LR; ++lj) {
+      if (lj == kb) {
+        if (tc == kc) {
 #pragma unroll
-      for (int lj = 0; lj <= li; ++lj) {
-        if (lj == kb && tc == kc) {
-          const int i = tr + G * li;
-          const cx<R> a = A[idx(li, lj)];
-          if (i > k && i < n) xb[i] = a;
-          if (i == k) d[k] = (double)a.re;
-          if (k == n - 2 && i == n - 1) {
-            const double ar = (double)a.re, ai = (double)a.im;
-            e2[k] = ar * ar + ai * ai;
+          for (int li = lj; li < LR; ++li) {
+            const int i = tr + G * li;
+            const cx<R> a = A[idx(li, lj)];
+            if (i > k && i < n) xb[i] = a;
+            if (i == k) d[k] = (double)a.re;
+            if (k == n - 2 && i == n - 1) {
+              const double ar = (double)a.re, ai = (double)a.im;
+              e2[k] = ar * ar + ai * ai;
+            }
           }
         }
-        if (k == n - 2 && lj == (n - 1) / G && li == lj && tr == (n - 1) % G && tc == (n - 1) % G)
-          d[n - 1] = (double)A[idx(li, lj)].re;
+      }
+    }
+    if (k == n - 2) {
+      const int lb = (n - 1) / G;
+      if (tr == (n - 1) % G && tc == (n - 1) % G) {
+#pragma unroll
+        for (int lj = 0; lj < LR; ++lj)
+          if (lj == lb) d[n - 1] = (double)A[idx(lj, lj)].re;
       }
     }
   }
@@ -139,43 +158,46 @@ struct ReduceLower {
         return {R(0), R(0)};
       };
       const int kb = (k + 1) / G;
-      // ---- y = B v : row partials (lower part) and column partials (upper part)
-      cx<R> vc[LR], yc[LR];
-#pragma unroll
-      for (int lj = 0; lj < LR; ++lj) {
-        vc[lj] = {R(0), R(0)};
-        yc[lj] = {R(0), R(0)};
-        if (lj >= kb) vc[lj] = vget(tc + G * lj);
+      // ---- y = B v : row partials (lower part) and column partials (upper part),
+      // column block by column block with v read from LDS, so that only the
+      // row partials stay in registers beside the matrix
+      cx<R>* vs = sm.vw[NVC == 1 ? 0 : tid >> 6];
+      if constexpr (NVC == 1) {
+        for (int i = kb * G + tid; i < NP; i += NT) vs[i] = vget(i);
+        __syncthreads();
+      } else {
+        for (int i = kb * G + lane; i < NP; i += 64) vs[i] = vget(i);
       }
       const R ms = (tr > tc) ? R(1) : R(0);
+      cx<R> yr[LR];
 #pragma unroll
-      for (int li = 0; li < LR; ++li) {
-        if (li < kb) continue;
-        const int i = tr + G * li;
-        const cx<R> vi = vget(i);
-        cx<R> yr = {R(0), R(0)};
-#pragma unroll
-        for (int lj = 0; lj < li; ++lj) {
-          if (lj < kb) continue;
-          const cx<R> a = A[idx(li, lj)];
-          yr.re += a.re * vc[lj].re - a.im * vc[lj].im;
-          yr.im += a.re * vc[lj].im + a.im * vc[lj].re;
-          yc[lj].re += a.re * vi.re + a.im * vi.im;
-          yc[lj].im += a.re * vi.im - a.im * vi.re;
-        }
-        {
-          const cx<R> a = A[idx(li, li)];
-          yr.re += a.re * vc[li].re - a.im * vc[li].im;
-          yr.im += a.re * vc[li].im + a.im * vc[li].re;
-          yc[li].re += ms * (a.re * vi.re + a.im * vi.im);
-          yc[li].im += ms * (a.re * vi.im - a.im * vi.re);
-        }
-        if (i > k && i < n) sm.pr[tc * PITCH + i] = yr;
-      }
+      for (int li = 0; li < LR; ++li) yr[li] = {R(0), R(0)};
 #pragma unroll
       for (int lj = 0; lj < LR; ++lj) {
+        if (lj < kb) continue;
+        const cx<R> vc = vs[tc + G * lj];
+        cx<R> yc = {R(0), R(0)};
+#pragma unroll
+        for (int li = lj; li < LR; ++li) {
+          const cx<R> vi = vs[tr + G * li];
+          const cx<R> a = A[idx(li, lj)];
+          yr[li].re += a.re * vc.re - a.im * vc.im;
+          yr[li].im += a.re * vc.im + a.im * vc.re;
+          if (li == lj) {  // diagonal block: strictly lower entries only
+            yc.re += ms * (a.re * vi.re + a.im * vi.im);
+            yc.im += ms * (a.re * vi.im - a.im * vi.re);
+          } else {
+            yc.re += a.re * vi.re + a.im * vi.im;
+            yc.im += a.re * vi.im - a.im * vi.re;
+          }
+        }
         const int j = tc + G * lj;
-        if (lj >= kb && j > k && j < n) sm.pc[tr * PITCH + j] = yc[lj];
+        if (j > k && j < n) sm.pc[tr * PITCH + j] = yc;
+      }
+#pragma unroll
+      for (int li = 0; li < LR; ++li) {
+        const int i = tr + G * li;
+        if (li >= kb && i > k && i < n) sm.pr[tc * PITCH + i] = yr[li];
       }
       __syncthreads();
       for (int i = k + 1 + tid; i < n; i += NT) {
@@ -202,33 +224,32 @@ struct ReduceLower {
         const cx<R> yy = sm.y[i];
         return {tre * yy.re - tim * yy.im - a2 * v.re, tre * yy.im + tim * yy.re - a2 * v.im};
       };
-      cx<R> wc[LR];
-#pragma unroll
-      for (int lj = 0; lj < LR; ++lj) {
-        wc[lj] = {R(0), R(0)};
-        if (lj >= kb) wc[lj] = wget(tc + G * lj, vc[lj]);
+      cx<R>* ws = sm.ww[NVC == 1 ? 0 : tid >> 6];
+      if constexpr (NVC == 1) {
+        for (int i = kb * G + tid; i < NP; i += NT) ws[i] = wget(i, vs[i]);
+        __syncthreads();
+      } else {
+        for (int i = kb * G + lane; i < NP; i += 64) ws[i] = wget(i, vs[i]);
       }
       // ---- B <- B - v w^H - w v^H on the stored lower triangle
       const R mr = (tr >= tc) ? R(1) : R(0);
 #pragma unroll
-      for (int li = 0; li < LR; ++li) {
-        if (li < kb) continue;
-        const int i = tr + G * li;
-        const cx<R> vi = vget(i);
-        const cx<R> wi = wget(i, vi);
+      for (int lj = 0; lj < LR; ++lj) {
+        if (lj < kb) continue;
+        const cx<R> vc = vs[tc + G * lj], wc = ws[tc + G * lj];
 #pragma unroll
-        for (int lj = 0; lj < li; ++lj) {
-          if (lj < kb) continue;
+        for (int li = lj; li < LR; ++li) {
+          const cx<R> vi = vs[tr + G * li], wi = ws[tr + G * li];
           cx<R>& a = A[idx(li, lj)];
-          a.re -= vi.re * wc[lj].re + vi.im * wc[lj].im + wi.re * vc[lj].re + wi.im * vc[lj].im;
-          a.im -= vi.im * wc[lj].re - vi.re * wc[lj].im + wi.im * vc[lj].re - wi.re * vc[lj].im;
-        }
-        {
-          cx<R>& a = A[idx(li, li)];
-          const R ur = vi.re * wc[li].re + vi.im * wc[li].im + wi.re * vc[li].re + wi.im * vc[li].im;
-          const R ui = vi.im * wc[li].re - vi.re * wc[li].im + wi.im * vc[li].re - wi.re * vc[li].im;
-          a.re -= mr * ur;
-          a.im -= ms * ui;
+          if (li > lj) {
+            a.re -= vi.re * wc.re + vi.im * wc.im + wi.re * vc.re + wi.im * vc.im;
+            a.im -= vi.im * wc.re - vi.re * wc.im + wi.im * vc.re - wi.re * vc.im;
+          } else {
+            const R ur = vi.re * wc.re + vi.im * wc.im + wi.re * vc.re + wi.im * vc.im;
+            const R ui = vi.im * wc.re - vi.re * wc.im + wi.im * vc.re - wi.re * vc.im;
+            a.re -= mr * ur;
+            a.im -= ms * ui;
+          }
         }
       }
       write_col(n, k + 1, A, sm.x[buf ^ 1], d, e2);
