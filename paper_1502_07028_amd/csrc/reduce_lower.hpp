@@ -9,26 +9,21 @@
 // lower triangle is stored (li >= lj, and inside a diagonal local block only
 // tr >= tc carries data, the rest stays zero).  y = A v is assembled from row
 // partials (lower part) and column partials (upper part, via conj(A_ji)) that
-// are summed through LDS.  The step algebra is that of reduce_full.hpp.  Both
-// the product and the rank-2 update walk the local blocks column block by
-// column block and read the row and column entries of v and w from LDS, so
-// that beside the matrix only the row partials of y live in registers (the
-// matrix takes most of the register file at n = 200 in FP64).
+// are summed through LDS.  The step algebra is that of reduce_full.hpp.  The
+// product takes the row partials and the column partials in two passes over
+// the stored blocks, and the rank-2 update walks them column block by column
+// block, all reading the entries of v and w from LDS, so that beside the
+// matrix only one accumulator lives in registers (the matrix takes most of the
+// register file at n = 200 in FP64).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <stdint.h>
 
 #include "cplx.hpp"
+#include "reduce_split.hpp"  // wave_total_rows, rsqrt_nr, fast_rcp
 
 namespace tca {
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <int G, int LR, typename R>
 struct ReduceLower {
@@ -131,20 +126,26 @@ struct ReduceLower {
         const cx<R> v = xk[i];
         s2 += v.re * v.re + v.im * v.im;
       }
-      s2 = wave_sum(s2);
+      s2 = wave_total_rows(s2);
       const cx<R> al = xk[k + 1];
       R beta, tre, tim, scr, sci;
       if (s2 == R(0) && al.im == R(0)) {
         beta = al.re;
         tre = tim = scr = sci = R(0);
       } else {
-        const R nrm = sqrt(al.re * al.re + al.im * al.im + s2);
-        beta = al.re >= R(0) ? -nrm : nrm;
-        tre = (beta - al.re) / beta;
-        tim = -al.im / beta;
-        const R dr = al.re - beta, di = al.im, den = dr * dr + di * di;
-        scr = dr / den;
-        sci = -di / den;
+        // one reciprocal square root and one reciprocal (the algebra of the
+        // split reducer's reflector): r = 1/|x|, sg = sign(Re alpha),
+        // beta = -sg |x|, tau = 1 + |Re alpha| r + i sg Im alpha r,
+        // 1/(alpha - beta) = (sg (|Re alpha| + |x|) - i Im alpha) / den
+        const R s = fma(al.re, al.re, fma(al.im, al.im, s2));
+        const R r = rsqrt_nr(s), nrm = s * r;
+        const R sg = al.re >= R(0) ? R(1) : R(-1), are = fabs(al.re), dr = are + nrm;
+        const R rden = fast_rcp(fma(dr, dr, al.im * al.im));
+        beta = -sg * nrm;
+        tre = fma(are, r, R(1));
+        tim = sg * al.im * r;
+        scr = sg * dr * rden;
+        sci = -al.im * rden;
       }
       if (tid == 0) {
         e2[k] = (double)beta * (double)beta;
@@ -169,20 +170,31 @@ struct ReduceLower {
         for (int i = kb * G + lane; i < NP; i += 64) vs[i] = vget(i);
       }
       const R ms = (tr > tc) ? R(1) : R(0);
-      cx<R> yr[LR];
+      // row partials, one accumulator per row block
 #pragma unroll
-      for (int li = 0; li < LR; ++li) yr[li] = {R(0), R(0)};
+      for (int li = 0; li < LR; ++li) {
+        if (li < kb) continue;
+        cx<R> yr = {R(0), R(0)};
+#pragma unroll
+        for (int lj = 0; lj <= li; ++lj) {
+          if (lj < kb) continue;
+          const cx<R> vc = vs[tc + G * lj];
+          const cx<R> a = A[idx(li, lj)];
+          yr.re += a.re * vc.re - a.im * vc.im;
+          yr.im += a.re * vc.im + a.im * vc.re;
+        }
+        const int i = tr + G * li;
+        if (i > k && i < n) sm.pr[tc * PITCH + i] = yr;
+      }
+      // column partials, one accumulator per column block
 #pragma unroll
       for (int lj = 0; lj < LR; ++lj) {
         if (lj < kb) continue;
-        const cx<R> vc = vs[tc + G * lj];
         cx<R> yc = {R(0), R(0)};
 #pragma unroll
         for (int li = lj; li < LR; ++li) {
           const cx<R> vi = vs[tr + G * li];
           const cx<R> a = A[idx(li, lj)];
-          yr[li].re += a.re * vc.re - a.im * vc.im;
-          yr[li].im += a.re * vc.im + a.im * vc.re;
           if (li == lj) {  // diagonal block: strictly lower entries only
             yc.re += ms * (a.re * vi.re + a.im * vi.im);
             yc.im += ms * (a.re * vi.im - a.im * vi.re);
@@ -193,11 +205,6 @@ struct ReduceLower {
         }
         const int j = tc + G * lj;
         if (j > k && j < n) sm.pc[tr * PITCH + j] = yc;
-      }
-#pragma unroll
-      for (int li = 0; li < LR; ++li) {
-        const int i = tr + G * li;
-        if (li >= kb && i > k && i < n) sm.pr[tc * PITCH + i] = yr[li];
       }
       __syncthreads();
       for (int i = k + 1 + tid; i < n; i += NT) {
@@ -217,7 +224,7 @@ struct ReduceLower {
         const cx<R> v = vget(i), yy = sm.y[i];
         c += v.re * yy.re + v.im * yy.im;
       }
-      c = wave_sum(c);
+      c = wave_total_rows(c);
       const R a2 = R(0.5) * (tre * tre + tim * tim) * c;
       auto wget = [&](int i, cx<R> v) -> cx<R> {
         if (i <= k || i >= n) return {R(0), R(0)};
