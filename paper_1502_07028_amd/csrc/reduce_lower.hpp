@@ -209,7 +209,7 @@ struct ReduceLower {
       __syncthreads();
       for (int i = k + 1 + tid; i < n; i += NT) {
         cx<R> s = {R(0), R(0)};
-#pragma unroll 4
+#pragma unroll
         for (int t = 0; t < G; ++t) {
           const cx<R> a = sm.pr[t * PITCH + i], b = sm.pc[t * PITCH + i];
           s.re += a.re + b.re;
