@@ -88,3 +88,15 @@ def test_strerror_and_abi_version():
     p.abi_version = 99
     with pytest.raises(tca.TCAError):
         tca.tca_init_lattice(p)
+
+def test_header_constants_match_binding():
+    """Every TCA_* enumerator of the header has the binding's value."""
+    import paper_1502_07028_amd as tca
+    txt = open(os.path.join(ROOT, "include", "tca.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    found = 0
+    for body in re.findall(r"enum\s*\{(.*?)\}", txt, flags=re.S):
+        for name, val in re.findall(r"(TCA_\w+)\s*=\s*(-?\d+)", body):
+            assert getattr(tca, name) == int(val), name
+            found += 1
+    assert found >= 10 and tca.TCA_FLAG_EXACT_METROPOLIS == 8
