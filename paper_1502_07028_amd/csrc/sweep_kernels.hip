@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kWaveMaxH) void decide_wave_kernel(
 // not change are read while d is decided); decisions and dE go to LDS, and the
 // spin writes, flags, records and counters follow in a parallel pass over the
 // block.  No global memory is read after the staging.
-constexpr int kStageMaxH = 24;  // 72 h^2 + 24 (h + 2)^2 + 9 h^2 bytes of LDS <= 62 KB
+constexpr int kStageMaxH = 24;  // 80 h^2 + 24 (h + 2)^2 + 9 h^2 bytes of LDS <= 66 KB
 
 static size_t decide_stage_lds_bytes(int h) {
   const size_t hh = (size_t)h * h, hf2 = (size_t)(h + 2) * (h + 2);
