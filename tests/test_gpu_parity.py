@@ -361,11 +361,12 @@ def test_autotuner_reports_choices(lib):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("n", [32, 50, 72, 80, 128, 162, 200])
+@pytest.mark.parametrize("n", [32, 50, 64, 72, 80, 128, 129, 162, 176, 177, 200])
 def test_every_reducer_variant(lib, n, precision):
     """Each reducer variant the autotuner may pick gives the LAPACK spectrum
     (FP64 to 1e-12 of the spectral scale, mixed to the FP32 bound), on random
-    Hermitian matrices of a ragged dimension."""
+    Hermitian matrices of ragged dimensions and of each class's padded size and
+    minimum."""
     names = lib.tca_reducer_variants(n, precision)
     A = np.stack([rand_hermitian(n, 40 + s) for s in range(3)])
     ref = np.stack([np.linalg.eigvalsh(a) for a in A])
