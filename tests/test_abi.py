@@ -76,6 +76,9 @@ def test_heevals_rejects_bad_sizes():
     assert e.value.status == tca.TCA_E_INVAL
     with pytest.raises(tca.TCAError):
         tca.tca_heevals_batched(np.zeros((1, 8, 8), complex), precision=3)
+    with pytest.raises(tca.TCAError) as e:  # a 1 x 1 matrix is its own eigenvalue
+        tca.tca_heevals_batched(np.zeros((1, 1, 1), complex))
+    assert e.value.status == tca.TCA_E_INVAL
 
 
 def test_strerror_and_abi_version():
