@@ -18,7 +18,10 @@ Large Lattices", arXiv:1502.07028):
 * the four-block visiting order of the parallel scheme, Sec. III(a) (Fig. 3),
   and a snapshot-batched variant of it used to check that the block schedule
   reproduces the sequential sweep;
-* the spin structure factor of Eq. (2).
+* the spin structure factor of Eq. (2);
+* the cluster matrix and classical energy of the Hubbard mean-field model the
+  paper benchmarks (Eq. (1)), in two and three dimensions (``hubbard_mf``;
+  the GPU path does not implement this model yet).
 
 Readings of points the paper leaves open (the double-exchange Hamiltonian, the
 free-energy formula, the RNG, the proposal distribution, where the classical
