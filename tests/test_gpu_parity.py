@@ -114,6 +114,35 @@ def test_heevals_empty_batch(lib):
     assert w.shape == (0, 8)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("Lc,d", [(4, 2), (2, 3), (4, 3)])
+def test_hubbard_mf_cluster_spectra(lib, Lc, d, precision):
+    """Cluster matrices of the paper's Hubbard mean-field benchmark model
+    (Eq. (1); the 3D 4^3 cluster gives n = 128) through the batched solver:
+    eigenvalues against LAPACK and grand potentials against the oracle, for
+    random fields of random length, a uniform field and m = 0 (degenerate)."""
+    from oracle import hubbard_mf as hmf
+    rng = np.random.default_rng(10 * Lc + d)
+    Nc, U = Lc ** d, 8.0
+    fields = []
+    for _ in range(4):
+        v = rng.normal(size=(Nc, 3))
+        fields.append(v / np.linalg.norm(v, axis=1, keepdims=True) * rng.uniform(0.0, 1.2, (Nc, 1)))
+    fields += [np.tile([0.0, 0.0, 0.8], (Nc, 1)), np.zeros((Nc, 3))]
+    A = np.stack([hmf.cluster_hamiltonian(m, Lc, d, 1.0, U) for m in fields])
+    n = A.shape[1]
+    T, mu = 0.1, U / 2
+    w, F = lib.tca_heevals_batched(A, precision, T=T, mu=mu)
+    for b in range(len(A)):
+        ref = eigen.eigvals_lapack(A[b])
+        scale = max(1.0, np.max(np.abs(ref)))
+        tol = 1e-12 * scale * max(1.0, n / 32) if precision == 0 else 2e-5 * scale * np.sqrt(n)
+        assert np.max(np.abs(w[b] - ref)) <= tol
+        Fref = otca.free_energy(ref, T, mu)
+        ftol = 1e-11 * max(1.0, abs(Fref)) if precision == 0 else n * tol
+        assert abs(F[b] - Fref) <= ftol
+
+
 @pytest.mark.parametrize("Lc", [2, 3, 4, 5, 6, 8, 10])
 def test_cluster_eigvals_ferro_closed_form(lib, Lc):
     lat = lib.Lattice(20, Lc, init=lib.TCA_INIT_FERRO)
